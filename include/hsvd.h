@@ -1,0 +1,138 @@
+/*
+ * hsvd.h -- C ABI of libhsvd.so: one-sided Jacobi hyperbolic SVD on MI355X (gfx950).
+ *
+ * Method: Novakovic & Singer, "A GPU-based hyperbolic SVD algorithm".
+ * For a square factor G (n x n, full column rank) and J = diag(+1 x p, -1 x (n-p))
+ * the library computes G = U Sigma V^T with U orthogonal and V^T J V = J
+ * (Sec. 1, eq. 1.1), and the eigenvalues Sigma^2 J of M = G J G^T (Sec. 1).
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are column-major FP64.  Every pointer argument named as "device"
+ *    is a device pointer on the context's device (e.g. a torch tensor's
+ *    data_ptr()); "host" pointers are ordinary host memory.
+ *  - The caller owns and allocates every input and output.  The library owns
+ *    its workspace (allocated on first use, grown on demand, released by
+ *    hsvd_destroy) and never frees or retains caller memory.
+ *  - All device work is enqueued on the context's stream.  Entry points that
+ *    return an hsvd_info synchronise with that stream before returning.
+ *  - Errors are returned as hsvd_status; nothing is thrown across the ABI.
+ *    On HSVD_E_INVAL nothing is launched.  On HSVD_E_NOCONV and HSVD_E_RANK
+ *    the outputs hold the current iterate.
+ *  - A context is not thread-safe: one host thread at a time per context.
+ */
+#ifndef HSVD_H
+#define HSVD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hsvd_ctx hsvd_ctx;
+
+typedef enum {
+    HSVD_OK = 0,
+    HSVD_E_INVAL = -1,   /* bad argument, non-finite input                          */
+    HSVD_E_NOCONV = -2,  /* max_sweeps reached without meeting the stop rule        */
+    HSVD_E_RANK = -3,    /* zero column, or a hyperbolic pair with |tanh 2phi| >= 1
+                            (G, or G J G^T, numerically rank deficient; Sec. 1)     */
+    HSVD_E_NOMEM = -4,   /* workspace allocation failed                             */
+    HSVD_E_DEVICE = -5   /* a HIP runtime call failed                               */
+} hsvd_status;
+
+typedef enum { HSVD_FP64 = 0, HSVD_MIXED = 1 } hsvd_precision;
+typedef enum { HSVD_AUTO = 0, HSVD_PAIRWISE = 1, HSVD_BLOCK = 2 } hsvd_algo;
+typedef enum { HSVD_ORD_MODMOD = 0, HSVD_ORD_ROUNDROBIN = 1 } hsvd_ordering;
+
+typedef struct {
+    int precision;   /* hsvd_precision; HSVD_FP64 is the pairwise / block FP64 path     */
+    int algo;        /* hsvd_algo                                                        */
+    int ordering;    /* hsvd_ordering: modified modulus (Sec. 2, Algs. 4.3-4.4) or the
+                        round-robin circle method starting on the same antidiagonal      */
+    int block;       /* block width b of the block path (0: library choice)             */
+    int sort;        /* 1: sort the diagonal before sweep 0 and after every sweep (Alg. 4.1) */
+    int want_v;      /* 1: accumulate V (V^{-T} of the paper, eq. 2.1)                   */
+    int max_sweeps;  /* <= 0: 100                                                        */
+    double tol;      /* threshold of the relative orthogonality test (eq. 2.3); <= 0: 1e-15 n */
+    double t_thresh; /* T of eq. (4.2); <= 0: sqrt(tol) / 2 (Sec. 2)                     */
+} hsvd_params;
+
+typedef struct {
+    int status;              /* same value as returned                                   */
+    int sweeps;              /* sweeps executed (the last one met the stop rule)         */
+    int code;                /* OR of the eq. (4.2) codes of the last sweep              */
+    int r;                   /* bordered order (eq. 4.1)                                 */
+    long long rotations;     /* rotations applied                                        */
+    long long skips;         /* pair visits skipped by eq. (2.3)                         */
+    long long steps;         /* parallel steps executed                                  */
+    double ms_total;         /* device time of the solve (event pair on the stream)      */
+    double ms_steps;         /* device time spent in the rotation-step kernels           */
+    long long step_launches; /* launches of the rotation-step kernel(s)                  */
+    double step_bytes;       /* algorithmic bytes moved by the step kernels (64 r per
+                                rotated pair, 16 r per skipped pair, FP64)               */
+    double step_flops;       /* algorithmic flops of the step kernels                    */
+} hsvd_info;
+
+/* Creates a context bound to HIP device `device` and stream `hip_stream`
+   (a hipStream_t; NULL = the device's null stream).  *ctx receives the
+   handle.  Errors: HSVD_E_INVAL (ctx NULL, bad device), HSVD_E_DEVICE. */
+hsvd_status hsvd_init(hsvd_ctx **ctx, int device, void *hip_stream);
+
+/* Releases the workspace and the handle (synchronises with the stream first). */
+hsvd_status hsvd_destroy(hsvd_ctx *ctx);
+
+/* Fills *prm with the defaults: FP64, AUTO, modified modulus, sort on, V on,
+   max_sweeps 100, tol and t_thresh from n at solve time. */
+void hsvd_default_params(hsvd_params *prm);
+
+/* One-sided Jacobi HSVD of a square G (Sec. 2 and Sec. 4, Algs. 4.1-4.5).
+ *   G       device, n x n, leading dimension lda >= n; read only (copied).
+ *   n, p    order and number of +1 signs in J (0 <= p <= n); J = diag(I_p, -I_{n-p}).
+ *   prm     host; NULL = defaults.
+ * Outputs (device, caller-allocated; any may be NULL except sigma):
+ *   sigma[n]   hyperbolic singular values, physical (input) column order.
+ *   U          n x n, ldu >= n: U = G_final Sigma^{-1} (Sec. 2).
+ *   V          n x n, ldv >= n: the accumulated V^{-T} of eq. (2.1), so that
+ *              G V = U Sigma and V^T J V = J; the paper's V is J V J.
+ *   lambda[n]  eigenvalues of G J G^T: sigma_c^2 times the sign of column c.
+ *   perm[n]    physical column index by final sorted position (rho of Fig. 4.1).
+ *   info       host; may be NULL.
+ * Odd n is bordered by a unit column with a negative sign (eq. 4.1); the
+ * border never appears in the outputs.  Errors: see hsvd_status. */
+hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p,
+                       const hsvd_params *prm, double *sigma, double *U, int ldu,
+                       double *V, int ldv, double *lambda, int *perm, hsvd_info *info);
+
+/* ---- Diagnostics: the individual steps of the path on caller data ---- */
+
+/* Elementwise skip test (eq. 2.3), rotation parameters (Sec. 2: t = tan / tanh
+ * of the angle that annihilates a_ij under eqs. 2.4/2.5, c = cos / cosh) and
+ * convergence code (eq. 4.2), computed by the device routine the solver uses.
+ *   m                      number of items.
+ *   aii, ajj, aij (device) m doubles each; hyp (device) m ints, -1 trig, +1 hyperbolic.
+ *   skip, status, code     (device) m ints out: 1 = skipped; 1 = rank failure; code.
+ *   t, c                   (device) m doubles out (t = 0, c = 1 when skipped).
+ * Synchronises.  Errors: HSVD_E_INVAL (m < 0, NULL arrays). */
+hsvd_status hsvd_pair_params(hsvd_ctx *ctx, long long m, const double *aii, const double *ajj,
+                             const double *aij, const int *hyp, double tol, double t_thresh,
+                             int *skip, double *t, double *c, int *status, int *code);
+
+/* Pivot pairs produced by the device stepper (Algs. 4.3-4.4, or round-robin)
+ * for `steps` consecutive steps starting at the first step of sweep 0.
+ *   r          even order (2 <= r).
+ *   pairs      device, steps x (r/2) x 2 ints out: (i, j), i < j, per slot.
+ * Synchronises.  Errors: HSVD_E_INVAL. */
+hsvd_status hsvd_pivot_trace(hsvd_ctx *ctx, int ordering, int r, int steps, int *pairs);
+
+/* Device diagonal sort (Sec. 4, Sort_Diagonal): stable; positions [0, p) by
+ * d decreasing, [p, r) by d increasing; rho travels with d.  In place on
+ *   d (device, r doubles), rho (device, r ints).  r <= 65536.
+ * Synchronises.  Errors: HSVD_E_INVAL. */
+hsvd_status hsvd_sort_diag(hsvd_ctx *ctx, int r, int p, double *d, int *rho);
+
+/* Library version string (static storage). */
+const char *hsvd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSVD_H */

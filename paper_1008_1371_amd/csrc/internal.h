@@ -1,0 +1,233 @@
+// Internal declarations of libhsvd: context, workspace layout, device helpers.
+//
+// Every floating point expression in the library is compiled with
+// -ffp-contract=off: an FMA appears only where fma() is written.  The rotation
+// parameter routine therefore rounds every operation separately, in the order
+// written, with correctly rounded division and square root.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/hsvd.h"
+
+namespace hsvd {
+
+constexpr int kMaxOrder = 16384;   // largest bordered order r (sort keeps r/1024 keys per thread)
+constexpr int kSortThreads = 1024;
+constexpr int kSortPerThread = kMaxOrder / kSortThreads;
+
+// Per-solve control block in device memory; copied to pinned host memory once per sweep.
+struct Ctl {
+    int code;          // OR of the eq. (4.2) codes of the sweep just reduced
+    int rank;          // set when a pair is numerically rank deficient
+    int inval;         // set when the input holds a non-finite value
+    int pad;
+    unsigned long long rot;    // rotations, cumulative
+    unsigned long long skip;   // skipped pair visits, cumulative
+};
+
+struct Workspace {
+    double *G = nullptr;      // ldg x r, working copy of G (bordered, zero-padded rows)
+    double *V = nullptr;      // ldg x r, accumulated V^{-T}
+    double *d = nullptr;      // r: kept diagonal, by position
+    int *rho = nullptr;       // r: physical column at each position
+    double *dtmp = nullptr;   // r: sort scratch
+    int *rtmp = nullptr;      // r: sort scratch
+    int4 *S = nullptr;        // r/2: modified modulus stepper state per slot (ip, jp, iblk, jblk)
+    int *C = nullptr;         // r/2: per-slot convergence code of the current sweep (eq. 4.2)
+    unsigned int *nrot = nullptr;   // r/2: per-slot rotations in the current sweep
+    unsigned int *nskip = nullptr;  // r/2: per-slot skips in the current sweep
+    Ctl *ctl = nullptr;
+};
+
+struct Layout {
+    int n = 0, r = 0, ldg = 0;
+    size_t bytes = 0;
+    size_t off_G, off_V, off_d, off_rho, off_dtmp, off_rtmp, off_S, off_C, off_nrot, off_nskip, off_ctl;
+};
+
+Layout make_layout(int n, int r, int ldg, bool want_v);
+Workspace carve(void *base, const Layout &L);
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+
+// Rotation parameters (Sec. 2): the angle annihilates a_ij under the column
+// updates (2.4) trig / (2.5) hyperbolic, i.e.
+//   tan 2phi = 2 a_ij / (a_jj - a_ii),   tanh 2phi = -2 a_ij / (a_ii + a_jj).
+// zeta = 1 / tan(h) 2phi; t is the root of smaller magnitude of
+// t^2 + 2 zeta t - 1 = 0 (trig) or t^2 - 2 zeta t + 1 = 0 (hyperbolic);
+// c = 1/sqrt(1 + t^2) or 1/sqrt((1 - t)(1 + t)).  sgn(0) = +1; for
+// |zeta| > 2^500, t = 0.5 / zeta.  Returns 1 (rank failure) for a hyperbolic
+// pair with |zeta| <= 1.
+__device__ __forceinline__ int rotation_params(double aii, double ajj, double aij, int hyp,
+                                               double &t, double &c)
+{
+    const double big = 0x1p500;
+    const double two_aij = 2.0 * aij;
+    if (hyp < 0) {
+        const double zeta = (ajj - aii) / two_aij;
+        const double az = fabs(zeta);
+        const double sg = zeta < 0.0 ? -1.0 : 1.0;
+        double tt;
+        if (az > big) {
+            tt = 0.5 / zeta;
+        } else {
+            const double root = sqrt(1.0 + zeta * zeta);
+            tt = sg / (az + root);
+        }
+        t = tt;
+        c = 1.0 / sqrt(1.0 + tt * tt);
+        return 0;
+    }
+    const double zeta = -(aii + ajj) / two_aij;
+    const double az = fabs(zeta);
+    if (!(az > 1.0)) {
+        t = 0.0;
+        c = 1.0;
+        return 1;
+    }
+    const double sg = zeta < 0.0 ? -1.0 : 1.0;
+    double tt;
+    if (az > big) {
+        tt = 0.5 / zeta;
+    } else {
+        const double root = sqrt(az - 1.0) * sqrt(az + 1.0);
+        tt = sg / (az + root);
+    }
+    t = tt;
+    c = 1.0 / sqrt((1.0 - tt) * (1.0 + tt));
+    return 0;
+}
+
+// Relative orthogonality, eq. (2.3), strict: |a_ij| < tol sqrt(a_ii) sqrt(a_jj).
+__device__ __forceinline__ bool rel_orthogonal(double aii, double ajj, double aij, double tol)
+{
+    return fabs(aij) < tol * (sqrt(aii) * sqrt(ajj));
+}
+
+// Eq. (4.2) code of one applied rotation, to be OR-ed into the slot's code.
+__device__ __forceinline__ int rotation_code(double t, double tthresh)
+{
+    return fabs(t) > tthresh ? 3 : 1;
+}
+
+// Modified modulus strategy: state (ip, jp, iblk, jblk) of one slot.
+// Start on the antidiagonal, slot k -> (k, r-1-k) (Alg. 4.3).
+__host__ __device__ __forceinline__ int4 modmod_start(int k, int r)
+{
+    return make_int4(k, r - 1 - k, k, r - 1 - k);
+}
+
+// Transition (Alg. 4.4) with the test read as ip + jp >= r - 1.
+__host__ __device__ __forceinline__ int4 modmod_next(int4 s, int r)
+{
+    if (s.x + s.y >= r - 1) {
+        s.x += 1;
+        if (s.x == s.y) {
+            s.x -= r / 2;
+            s.y = s.x;
+        }
+        s.z = s.x;
+    } else {
+        s.y += 1;
+        s.w = s.y;
+    }
+    return s;
+}
+
+// Round-robin circle method: arrangement A_s[0] = 0,
+// A_s[m] = 1 + ((m - 1 + s) mod (r - 1)); slot k pairs A_s[k] with A_s[r-1-k].
+__host__ __device__ __forceinline__ int2 roundrobin_pair(int k, int r, int s)
+{
+    const int a = (k == 0) ? 0 : 1 + ((k - 1 + s) % (r - 1));
+    const int b = 1 + ((r - 2 - k + s) % (r - 1));
+    return a < b ? make_int2(a, b) : make_int2(b, a);
+}
+
+// Sum over a 64-lane wavefront by an xor butterfly; every lane ends with the
+// same bits (each stage adds the same two operands, in either order).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Sum over a workgroup of WG threads; all threads return the same bits.
+// `sh` holds WG/64 doubles.
+template <int WG>
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    v = wave_sum(v);
+    if (WG == 64) return v;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = sh[0];
+#pragma unroll
+    for (int q = 1; q < WG / 64; ++q) s += sh[q];
+    __syncthreads();
+    return s;
+}
+
+template <int WG>
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *sh)
+{
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (WG == 64) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[2 * w] = a;
+        sh[2 * w + 1] = b;
+    }
+    __syncthreads();
+    double sa = sh[0], sb = sh[1];
+#pragma unroll
+    for (int q = 1; q < WG / 64; ++q) {
+        sa += sh[2 * q];
+        sb += sh[2 * q + 1];
+    }
+    __syncthreads();
+    a = sa;
+    b = sb;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (pairwise path), all on `st`.
+// ---------------------------------------------------------------------------
+struct StepArgs {
+    double *G;
+    double *V;       // nullptr: no V accumulation
+    int ldg, r, p;
+    double *d;
+    const int *rho;
+    int4 *S;
+    int *C;
+    unsigned int *nrot, *nskip;
+    Ctl *ctl;
+    int ordering;    // HSVD_ORD_MODMOD / HSVD_ORD_ROUNDROBIN
+    int step;        // step index inside the sweep (round-robin)
+    double tol, tthresh;
+};
+
+hipError_t launch_setup(hipStream_t st, const double *G, int lda, int n, const Workspace &w,
+                        int r, int ldg, bool want_v);
+hipError_t launch_precompute(hipStream_t st, const Workspace &w, int r, int ldg);
+hipError_t launch_pair_step(hipStream_t st, const StepArgs &a);
+hipError_t launch_sort(hipStream_t st, double *d, int *rho, double *dtmp, int *rtmp, int r, int p);
+hipError_t launch_sweep_reduce(hipStream_t st, const Workspace &w, int slots);
+hipError_t launch_finalize(hipStream_t st, const Workspace &w, int n, int r, int p, int ldg,
+                           double *sigma, double *U, int ldu, double *V, int ldv, double *lambda,
+                           int *perm);
+hipError_t launch_pair_params(hipStream_t st, long long m, const double *aii, const double *ajj,
+                              const double *aij, const int *hyp, double tol, double tthresh,
+                              int *skip, double *t, double *c, int *status, int *code);
+hipError_t launch_pivot_trace(hipStream_t st, int ordering, int r, int steps, int *pairs);
+hipError_t launch_zero_ctl(hipStream_t st, Ctl *ctl);
+
+}  // namespace hsvd

@@ -1,0 +1,236 @@
+"""ctypes binding of libhsvd.so (include/hsvd.h).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  Matrices are passed
+as torch tensors holding the mathematical matrix; a column-major view
+(``X.t()`` of a contiguous ``X``) is passed through without a copy, anything
+else is copied to column-major storage first.
+
+Importing this module does not touch the GPU.  Loading the library fails
+loudly when it has not been built (``python -m paper_1008_1371_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhsvd.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "hsvd.h")
+
+OK, E_INVAL, E_NOCONV, E_RANK, E_NOMEM, E_DEVICE = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOCONV", -3: "E_RANK", -4: "E_NOMEM",
+                -5: "E_DEVICE"}
+FP64, MIXED = 0, 1
+AUTO, PAIRWISE, BLOCK = 0, 1, 2
+MODMOD, ROUNDROBIN = 0, 1
+
+
+class hsvd_params(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("algo", ctypes.c_int), ("ordering", ctypes.c_int),
+                ("block", ctypes.c_int), ("sort", ctypes.c_int), ("want_v", ctypes.c_int),
+                ("max_sweeps", ctypes.c_int), ("tol", ctypes.c_double),
+                ("t_thresh", ctypes.c_double)]
+
+
+class hsvd_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("sweeps", ctypes.c_int), ("code", ctypes.c_int),
+                ("r", ctypes.c_int), ("rotations", ctypes.c_longlong),
+                ("skips", ctypes.c_longlong), ("steps", ctypes.c_longlong),
+                ("ms_total", ctypes.c_double), ("ms_steps", ctypes.c_double),
+                ("step_launches", ctypes.c_longlong), ("step_bytes", ctypes.c_double),
+                ("step_flops", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def header_functions(path: str = HEADER):
+    """Names of the functions declared in include/hsvd.h."""
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return re.findall(r"\b(hsvd_\w+)\s*\(", txt)
+
+
+def lib():
+    """Loads libhsvd.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1008_1371_amd.build` (there is no fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.hsvd_init.argtypes = [ctypes.POINTER(vp), ip, vp]
+    L.hsvd_destroy.argtypes = [vp]
+    L.hsvd_default_params.argtypes = [ctypes.POINTER(hsvd_params)]
+    L.hsvd_default_params.restype = None
+    L.hsvd_solve.argtypes = [vp, vp, ip, ip, ip, ctypes.POINTER(hsvd_params), vp, vp, ip, vp, ip,
+                             vp, vp, ctypes.POINTER(hsvd_info)]
+    L.hsvd_pair_params.argtypes = [vp, ctypes.c_longlong, vp, vp, vp, vp, dp, dp, vp, vp, vp, vp,
+                                   vp]
+    L.hsvd_pivot_trace.argtypes = [vp, ip, ip, ip, vp]
+    L.hsvd_sort_diag.argtypes = [vp, ip, ip, vp, vp]
+    L.hsvd_version.restype = ctypes.c_char_p
+    for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_pair_params",
+                 "hsvd_pivot_trace", "hsvd_sort_diag"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+class HsvdError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}")
+        self.status = status
+
+
+def _check(st, what):
+    if st != OK:
+        raise HsvdError(st, what)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _colmajor(G):
+    """Returns (tensor, ld) with column-major storage of the matrix G."""
+    import torch  # noqa: F401  (device memory and streams only)
+    n0, n1 = G.shape
+    if G.stride(0) == 1 and G.stride(1) >= max(1, n0):
+        return G, G.stride(1)
+    Gc = G.t().contiguous().t()
+    return Gc, n0
+
+
+def _new_colmajor(n, device, dtype):
+    import torch
+    return torch.empty((n, n), dtype=dtype, device=device).t()
+
+
+class Context:
+    """An hsvd_ctx bound to a device and a stream (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = ctypes.c_void_p()
+        _check(L.hsvd_init(ctypes.byref(h), int(device), ctypes.c_void_p(stream)), "hsvd_init")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().hsvd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def hsvd_init(device: int = 0, stream=None) -> Context:
+    return Context(device, stream)
+
+
+def hsvd_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def hsvd_default_params(**overrides) -> hsvd_params:
+    prm = hsvd_params()
+    lib().hsvd_default_params(ctypes.byref(prm))
+    for k, v in overrides.items():
+        setattr(prm, k, v)
+    return prm
+
+
+def hsvd_solve(ctx: Context, G, p: int, params: hsvd_params | None = None, *, want_u=True,
+               want_v=None, want_lambda=True, want_perm=True, out=None, check=True):
+    """Solves G = U Sigma V^T, V^T J V = J with J = diag(I_p, -I_{n-p}).
+
+    G: square float64 CUDA tensor.  Returns a dict with sigma, U, V, lambda,
+    perm (tensors or None), status and info (a dict).  ``out`` may hold
+    preallocated output tensors with the same keys."""
+    import torch
+    L = lib()
+    n = G.shape[0]
+    assert G.shape == (n, n) and G.dtype == torch.float64 and G.is_cuda
+    prm = params if params is not None else hsvd_default_params()
+    if want_v is None:
+        want_v = bool(prm.want_v)
+    Gc, lda = _colmajor(G)
+    out = dict(out or {})
+    dev = G.device
+    sigma = out.get("sigma")
+    if sigma is None:
+        sigma = torch.empty(n, dtype=torch.float64, device=dev)
+    U = out.get("U") if want_u else None
+    if want_u and U is None:
+        U = _new_colmajor(n, dev, torch.float64)
+    V = out.get("V") if want_v else None
+    if want_v and V is None:
+        V = _new_colmajor(n, dev, torch.float64)
+    lam = out.get("lambda") if want_lambda else None
+    if want_lambda and lam is None:
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+    perm = out.get("perm") if want_perm else None
+    if want_perm and perm is None:
+        perm = torch.empty(n, dtype=torch.int32, device=dev)
+    info = hsvd_info()
+    st = L.hsvd_solve(ctx.handle, _ptr(Gc), lda, n, int(p), ctypes.byref(prm), _ptr(sigma),
+                      _ptr(U), U.stride(1) if U is not None else n, _ptr(V),
+                      V.stride(1) if V is not None else n, _ptr(lam), _ptr(perm),
+                      ctypes.byref(info))
+    if check and st not in (OK,):
+        raise HsvdError(st, "hsvd_solve")
+    return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, perm=perm, info=info.as_dict())
+
+
+def hsvd_pair_params(ctx: Context, aii, ajj, aij, hyp, tol: float, t_thresh: float):
+    import torch
+    m = aii.numel()
+    dev = aii.device
+    skip = torch.empty(m, dtype=torch.int32, device=dev)
+    status = torch.empty(m, dtype=torch.int32, device=dev)
+    code = torch.empty(m, dtype=torch.int32, device=dev)
+    t = torch.empty(m, dtype=torch.float64, device=dev)
+    c = torch.empty(m, dtype=torch.float64, device=dev)
+    _check(lib().hsvd_pair_params(ctx.handle, m, _ptr(aii), _ptr(ajj), _ptr(aij), _ptr(hyp),
+                                  float(tol), float(t_thresh), _ptr(skip), _ptr(t), _ptr(c),
+                                  _ptr(status), _ptr(code)), "hsvd_pair_params")
+    return dict(skip=skip, t=t, c=c, status=status, code=code)
+
+
+def hsvd_pivot_trace(ctx: Context, ordering: int, r: int, steps: int):
+    import torch
+    pairs = torch.empty((steps, r // 2, 2), dtype=torch.int32, device=f"cuda:{ctx.device}")
+    _check(lib().hsvd_pivot_trace(ctx.handle, int(ordering), int(r), int(steps), _ptr(pairs)),
+           "hsvd_pivot_trace")
+    return pairs
+
+
+def hsvd_sort_diag(ctx: Context, d, rho, p: int):
+    _check(lib().hsvd_sort_diag(ctx.handle, d.numel(), int(p), _ptr(d), _ptr(rho)),
+           "hsvd_sort_diag")
+    return d, rho
+
+
+def hsvd_version() -> str:
+    return lib().hsvd_version().decode()

@@ -1,0 +1,82 @@
+"""Bit-exact gates of the individual steps on identical inputs (GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_triples(m, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    aii = 10.0 ** g.uniform(-30, 30, m)
+    ajj = aii * 10.0 ** g.uniform(-12, 12, m)
+    # |a_ij| <= sqrt(a_ii a_jj) (a Gram matrix), with many near-equal / near-parallel cases
+    cosang = g.uniform(-1, 1, m) ** g.choice([1, 3, 9], m)
+    aij = cosang * np.sqrt(aii) * np.sqrt(ajj)
+    eq = g.uniform(size=m) < 0.05
+    ajj[eq] = aii[eq]
+    tiny = g.uniform(size=m) < 0.05
+    aij[tiny] *= 1e-17
+    hyp = np.where(g.uniform(size=m) < 0.5, -1, 1).astype(np.int32)
+    return aii, ajj, aij, hyp
+
+
+def test_pair_params_bit_exact(hsvd_ctx):
+    import torch
+
+    from paper_1008_1371_amd import hsvd as H
+    m = 1_000_000
+    aii, ajj, aij, hyp = _random_triples(m, 123)
+    edge = np.array([[2.0, 2.0, 0.5, -1], [2.0, 2.0, -0.5, -1], [4.0, 4.0, 4.0, 1],
+                     [4.0, 4.0, -4.0, 1], [3.0, 1.0, 1e-200, -1], [3.0, 1.0, 1e-200, 1],
+                     [4.0, 4.0, 1.0, -1], [1.0, 1e-300, 1e-151, 1], [1e300, 1e300, 1e299, 1]])
+    aii = np.r_[aii, edge[:, 0]]
+    ajj = np.r_[ajj, edge[:, 1]]
+    aij = np.r_[aij, edge[:, 2]]
+    hyp = np.r_[hyp, edge[:, 3].astype(np.int32)]
+    tol, T = 1e-13, 0.5e-6
+    say("pair_params", aii.size)
+    want = oracle.pair_params_batch(aii, ajj, aij, hyp, tol, T)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    got = H.hsvd_pair_params(hsvd_ctx, dev(aii), dev(ajj), dev(aij), dev(hyp), tol, T)
+    for k in ("skip", "status", "code"):
+        assert np.array_equal(got[k].cpu().numpy(), want[k]), k
+    for k in ("t", "c"):
+        g = got[k].cpu().numpy()
+        bad = np.flatnonzero(g.view(np.int64) != want[k].view(np.int64))
+        assert bad.size == 0, (k, bad[:5], g[bad[:5]], want[k][bad[:5]])
+
+
+@pytest.mark.parametrize("r", [2, 4, 8, 10, 130, 1024, 4096])
+@pytest.mark.parametrize("ordering", ["modmod", "roundrobin"])
+def test_pivot_trace_bit_exact(hsvd_ctx, r, ordering):
+    from paper_1008_1371_amd import hsvd as H
+    steps = 2 * r + 1 if r <= 1024 else r + 1
+    say("pivot_trace", ordering, r, steps)
+    if ordering == "modmod":
+        want = oracle.modmod_trace(r, steps)
+        got = H.hsvd_pivot_trace(hsvd_ctx, H.MODMOD, r, steps).cpu().numpy()
+    else:
+        want = oracle.roundrobin_trace(r, steps)
+        got = H.hsvd_pivot_trace(hsvd_ctx, H.ROUNDROBIN, r, steps).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("r,p", [(1, 0), (1, 1), (7, 3), (128, 64), (1000, 0), (1000, 1000),
+                                 (4096, 2048), (8194, 3000), (16384, 100)])
+def test_sort_bit_exact(hsvd_ctx, r, p):
+    import torch
+
+    from paper_1008_1371_amd import hsvd as H
+    g = np.random.Generator(np.random.PCG64(r + p))
+    d = np.round(g.uniform(0, 8, r) * 4) / 4  # ties
+    d[: r // 3] = g.uniform(0, 8, r // 3)
+    rho = g.permutation(r).astype(np.int32)
+    say("sort", r, p)
+    wd, wr = oracle.sort_diag(d, rho, p)
+    dd = torch.from_numpy(d.copy()).cuda()
+    rr = torch.from_numpy(rho.copy()).cuda()
+    H.hsvd_sort_diag(hsvd_ctx, dd, rr, p)
+    assert np.array_equal(dd.cpu().numpy(), wd) and np.array_equal(rr.cpu().numpy(), wr)
