@@ -27,10 +27,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="colscaled4096")
-    ap.add_argument("--path", default="pairwise", choices=["pairwise"])
-    ap.add_argument("--cpu-sample-steps", type=int, default=96)
+    ap.add_argument("--path", default="block", choices=["pairwise", "block"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the bounded oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--max-sweeps", type=int, default=0,
+                    help="stop each solve after this many sweeps (profiling runs only)")
     return ap.parse_args()
 
 
@@ -53,18 +56,55 @@ def accuracy(G, p, R):
     return out
 
 
-def cpu_baseline(G_np, p, sample_steps, total_steps, path):
+def cpu_baseline(G_np, p, total_steps, block, target_s):
+    """The oracle (same ordering as the GPU path) timed on the first outer steps
+    of the same solve; the solve time is extrapolated linearly in steps."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    R = oracle.hsvd(G_np, p, max_steps=sample_steps, nthreads=threads)
+    oracle.hsvd(G_np, p, max_steps=2, nthreads=threads, block=block)
+    probe = time.perf_counter() - t0
+    steps = int(max(2, min(total_steps, 2 * target_s / max(probe, 1e-6))))
+    t0 = time.perf_counter()
+    R = oracle.hsvd(G_np, p, max_steps=steps, nthreads=threads, block=block)
     dt = time.perf_counter() - t0
-    per_step = dt / max(1, R["steps"])
-    est_solve = per_step * total_steps
+    est_solve = dt / max(1, R["steps"]) * total_steps
+    mode = f"block ordering, b={block}" if block else "pairwise modified modulus"
     return {"value": 1.0 / est_solve, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle ({path} ordering) on the same input for the first {R['steps']} of "
-                       f"the {total_steps} parallel steps the GPU solve took ({dt:.1f} s); "
-                       f"solve time extrapolated linearly in steps: {est_solve:.0f} s")}
+            "sample": (f"oracle ({mode}) on the same input for the first {R['steps']} of the "
+                       f"{total_steps} outer steps the GPU solve took ({dt:.1f} s); solve time "
+                       f"extrapolated linearly in steps: {est_solve:.0f} s")}
+
+
+def roofline(infos, names):
+    """Roofline of the kernel class with the most measured time."""
+    nk = len(names)
+    ms = [sum(i["kernel_ms"][q] for i in infos) for q in range(nk)]
+    q = max(range(nk), key=lambda k: ms[k])
+    launches = sum(i["kernel_launches"][q] for i in infos)
+    byts = sum(i["kernel_bytes"][q] for i in infos)
+    flops = sum(i["kernel_flops"][q] for i in infos)
+    avg_s = ms[q] * 1e-3 / launches
+    bpl, fpl = byts / launches, flops / launches
+    if flops > 0 and flops / byts * HBM_PEAK_GBS * 1e9 > FP64_PEAK_TFLOPS * 1e12:
+        ach = fpl / avg_s / 1e12
+        r = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+             "frac": ach / FP64_PEAK_TFLOPS}
+    else:
+        ach = bpl / avg_s / 1e9
+        r = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": ach / HBM_PEAK_GBS}
+    r.update({"traffic": None, "kernel": names[q], "avg_launch_us": avg_s * 1e6,
+              "bytes_per_launch": bpl, "flops_per_launch": fpl,
+              "share_of_solve": ms[q] / sum(i["ms_total"] for i in infos)})
+    other = {}
+    for k in range(nk):
+        L = sum(i["kernel_launches"][k] for i in infos)
+        if L:
+            other[names[k]] = {"avg_launch_us": ms[k] * 1e3 / L, "launches_per_solve": L / len(infos),
+                               "ms_per_solve": ms[k] / len(infos)}
+    r["kernels"] = other
+    return r
 
 
 def main():
@@ -85,7 +125,11 @@ def main():
     dev = torch.device("cuda:0")
     G = torch.from_numpy(np.asfortranarray(G_np)).to(dev)
     ctx = H.Context(0)
-    prm = H.hsvd_default_params(algo=H.PAIRWISE)
+    prm = H.hsvd_default_params(algo=H.PAIRWISE if args.path == "pairwise" else H.BLOCK)
+    check = True
+    if args.max_sweeps > 0:
+        prm.max_sweeps = args.max_sweeps
+        check = False
     out = dict(
         sigma=torch.empty(n, dtype=torch.float64, device=dev),
         U=torch.empty((n, n), dtype=torch.float64, device=dev).t(),
@@ -94,23 +138,17 @@ def main():
         perm=torch.empty(n, dtype=torch.int32, device=dev),
     )
     for _ in range(args.warmup):
-        H.hsvd_solve(ctx, G, p, prm, out=out)
+        H.hsvd_solve(ctx, G, p, prm, out=out, check=check)
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        R = H.hsvd_solve(ctx, G, p, prm, out=out)
+        R = H.hsvd_solve(ctx, G, p, prm, out=out, check=check)
         infos.append(R["info"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1000.0 * wall / args.steps
 
-    ms_steps = sum(i["ms_steps"] for i in infos)
-    launches = sum(i["step_launches"] for i in infos)
-    step_bytes = sum(i["step_bytes"] for i in infos)
-    avg_launch_ms = ms_steps / launches
-    bytes_per_launch = step_bytes / launches
-    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     last = infos[-1]
     line = {
         "metric": METRIC,
@@ -125,21 +163,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "p": p, "path": "pairwise-fp64",
-                   "ordering": "modmod", "sort": 1, "want_v": 1, "tol": 1e-15 * n,
-                   "sweeps": last["sweeps"], "rotations": last["rotations"],
-                   "steps_per_solve": last["steps"]},
-        "roofline": {"bound": "hbm", "kernel": "pair_step_kernel",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_us": avg_launch_ms * 1e3,
-                     "bytes_per_launch": bytes_per_launch},
+        "config": {"workload": args.workload, "n": n, "p": p,
+                   "path": f"{args.path}-fp64", "block": last["block"], "ordering": "modmod",
+                   "sort": 1, "want_v": 1, "tol": 1e-15 * n, "sweeps": last["sweeps"],
+                   "rotations": last["rotations"], "steps_per_solve": last["steps"]},
+        "roofline": roofline(infos, H.KERNEL_NAMES),
     }
     if not args.no_accuracy:
         line["accuracy"] = accuracy(G, p, R)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(G_np, p, args.cpu_sample_steps, last["steps"],
-                                            "pairwise modmod")
+        line["cpu_baseline"] = cpu_baseline(G_np, p, last["steps"], last["block"],
+                                            args.cpu_seconds)
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -48,7 +48,7 @@ typedef struct {
     int algo;        /* hsvd_algo                                                        */
     int ordering;    /* hsvd_ordering: modified modulus (Sec. 2, Algs. 4.3-4.4) or the
                         round-robin circle method starting on the same antidiagonal      */
-    int block;       /* block width b of the block path (0: library choice)             */
+    int block;       /* block width b of the block path: 0 or 32                          */
     int sort;        /* 1: sort the diagonal before sweep 0 and after every sweep (Alg. 4.1) */
     int want_v;      /* 1: accumulate V (V^{-T} of the paper, eq. 2.1)                   */
     int max_sweeps;  /* <= 0: 100                                                        */
@@ -56,20 +56,31 @@ typedef struct {
     double t_thresh; /* T of eq. (4.2); <= 0: sqrt(tol) / 2 (Sec. 2)                     */
 } hsvd_params;
 
+/* Kernel classes timed in hsvd_info (index into the kernel_* arrays). */
+enum {
+    HSVD_K_PAIR_STEP = 0,    /* pairwise path: one parallel step of pivot pairs            */
+    HSVD_K_BLOCK_GRAM = 1,   /* block path: Gram matrices G_P^T G_P of the block pairs      */
+    HSVD_K_BLOCK_INNER = 2,  /* block path: inner rotations of each block pair             */
+    HSVD_K_BLOCK_UPDATE = 3, /* block path: [G_P | V_P] <- [G_P | V_P] W                   */
+    HSVD_NKERNELS = 4
+};
+
 typedef struct {
     int status;              /* same value as returned                                   */
     int sweeps;              /* sweeps executed (the last one met the stop rule)         */
     int code;                /* OR of the eq. (4.2) codes of the last sweep              */
     int r;                   /* bordered order (eq. 4.1)                                 */
+    int block;               /* block width b used; 0 = pairwise path                    */
+    int ldg;                 /* padded leading dimension of the working copies           */
     long long rotations;     /* rotations applied                                        */
     long long skips;         /* pair visits skipped by eq. (2.3)                         */
-    long long steps;         /* parallel steps executed                                  */
+    long long steps;         /* parallel (outer) steps executed                          */
+    long long active_pairs;  /* block pair steps with at least one rotation              */
     double ms_total;         /* device time of the solve (event pair on the stream)      */
-    double ms_steps;         /* device time spent in the rotation-step kernels           */
-    long long step_launches; /* launches of the rotation-step kernel(s)                  */
-    double step_bytes;       /* algorithmic bytes moved by the step kernels (64 r per
-                                rotated pair, 16 r per skipped pair, FP64)               */
-    double step_flops;       /* algorithmic flops of the step kernels                    */
+    double kernel_ms[HSVD_NKERNELS];         /* device time per kernel class            */
+    long long kernel_launches[HSVD_NKERNELS];
+    double kernel_bytes[HSVD_NKERNELS];      /* algorithmic bytes (see the design notes) */
+    double kernel_flops[HSVD_NKERNELS];      /* algorithmic flops                        */
 } hsvd_info;
 
 /* Creates a context bound to HIP device `device` and stream `hip_stream`
@@ -123,9 +134,20 @@ hsvd_status hsvd_pair_params(hsvd_ctx *ctx, long long m, const double *aii, cons
  * Synchronises.  Errors: HSVD_E_INVAL. */
 hsvd_status hsvd_pivot_trace(hsvd_ctx *ctx, int ordering, int r, int steps, int *pairs);
 
+/* Block-path pivot positions of `steps` consecutive outer steps from the
+ * start of sweep 0 (outer ordering over nb = r/b blocks; inner ordering of
+ * each block pair as used by the solver).
+ *   r, b       r a multiple of 2b; b = 32 (the block width the library runs).
+ *   pairs      device ints out, concatenated over the steps: step s contributes
+ *              (nb/2) x inner(s) x b pairs (i, j), i < j, ordered by block pair,
+ *              inner step, slot; inner(s) = 2b - 1 at the first step of a sweep,
+ *              else b.
+ * Synchronises.  Errors: HSVD_E_INVAL. */
+hsvd_status hsvd_block_trace(hsvd_ctx *ctx, int ordering, int r, int b, int steps, int *pairs);
+
 /* Device diagonal sort (Sec. 4, Sort_Diagonal): stable; positions [0, p) by
  * d decreasing, [p, r) by d increasing; rho travels with d.  In place on
- *   d (device, r doubles), rho (device, r ints).  r <= 65536.
+ *   d (device, r doubles), rho (device, r ints).  r <= 16384.
  * Synchronises.  Errors: HSVD_E_INVAL. */
 hsvd_status hsvd_sort_diag(hsvd_ctx *ctx, int r, int p, double *d, int *rho);
 

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhsvd.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.hip", "pair_kernels.hip"]
+SOURCES = ["api.hip", "pair_kernels.hip", "block_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -26,6 +26,7 @@ struct Ctl {
     int pad;
     unsigned long long rot;    // rotations, cumulative
     unsigned long long skip;   // skipped pair visits, cumulative
+    unsigned long long act;    // block pair steps with a rotation, cumulative
 };
 
 struct Workspace {
@@ -39,16 +40,24 @@ struct Workspace {
     int *C = nullptr;         // r/2: per-slot convergence code of the current sweep (eq. 4.2)
     unsigned int *nrot = nullptr;   // r/2: per-slot rotations in the current sweep
     unsigned int *nskip = nullptr;  // r/2: per-slot skips in the current sweep
+    unsigned int *nact = nullptr;   // r/2: per-slot steps with at least one rotation (block path)
     Ctl *ctl = nullptr;
+    // block path
+    double *P = nullptr;      // pairs x splits x (2b)^2 partial Gram matrices
+    double *W = nullptr;      // pairs x (2b)^2 accumulated inner transformations
+    int *active = nullptr;    // pairs: 1 when the pair's W is not the identity
+    int4 *S2 = nullptr;       // 2 x pairs: outer stepper state, double-buffered across steps
 };
 
 struct Layout {
-    int n = 0, r = 0, ldg = 0;
+    int n = 0, r = 0, ldg = 0, pairs = 0, splits = 0, b2 = 0;
     size_t bytes = 0;
-    size_t off_G, off_V, off_d, off_rho, off_dtmp, off_rtmp, off_S, off_C, off_nrot, off_nskip, off_ctl;
+    size_t off_G, off_V, off_d, off_rho, off_dtmp, off_rtmp, off_S, off_C, off_nrot, off_nskip,
+        off_nact, off_ctl, off_P, off_W, off_active, off_S2;
 };
 
-Layout make_layout(int n, int r, int ldg, bool want_v);
+// pairs/splits/b2 > 0 adds the block path buffers.
+Layout make_layout(int n, int r, int ldg, bool want_v, int pairs = 0, int splits = 0, int b2 = 0);
 Workspace carve(void *base, const Layout &L);
 
 // ---------------------------------------------------------------------------
@@ -148,6 +157,15 @@ __host__ __device__ __forceinline__ int2 roundrobin_pair(int k, int r, int s)
     return a < b ? make_int2(a, b) : make_int2(b, a);
 }
 
+// Inner ordering of a block pair, local indices x < y in [0, 2b), slot q < b,
+// inner step u: first outer step of a sweep -> circle method over 2b indices
+// (2b - 1 inner steps); otherwise the cross pair (q, b + ((q + u) mod b)).
+__host__ __device__ __forceinline__ int2 block_inner_pair(int q, int u, bool first, int b)
+{
+    if (first) return roundrobin_pair(q, 2 * b, u);
+    return make_int2(q, b + ((q + u) % b));
+}
+
 // Sum over a 64-lane wavefront by an xor butterfly; every lane ends with the
 // same bits (each stage adds the same two operands, in either order).
 __device__ __forceinline__ double wave_sum(double v)
@@ -214,6 +232,33 @@ struct StepArgs {
     int step;        // step index inside the sweep (round-robin)
     double tol, tthresh;
 };
+
+struct BlockArgs {
+    double *G;
+    double *V;               // nullptr: no V accumulation
+    int ldg, r, p, nb;
+    const int *rho;
+    const int4 *S_in;        // outer stepper state of this step
+    int4 *S_out;             // state of the next step (written by the update kernel)
+    int ordering, step;      // step: outer step index inside the sweep
+    double *partial;
+    int splits, rows_per_split;
+    double *W;
+    int *active;
+    int *C;
+    unsigned int *nrot, *nskip, *nact;
+    Ctl *ctl;
+    double tol, tthresh;
+};
+
+int block_width();
+hipError_t launch_block_stepper_init(hipStream_t st, int4 *S, int nb);
+hipError_t launch_block_gram(hipStream_t st, const BlockArgs &a);
+hipError_t launch_block_inner(hipStream_t st, const BlockArgs &a);
+hipError_t launch_block_update(hipStream_t st, const BlockArgs &a);
+hipError_t launch_colnorm_pos(hipStream_t st, const double *G, int ldg, const int *rho, double *d, int r);
+hipError_t launch_block_trace(hipStream_t st, int ordering, int r, int b, int step, int4 *S, int *out,
+                              bool advance);
 
 hipError_t launch_setup(hipStream_t st, const double *G, int lda, int n, const Workspace &w,
                         int r, int ldg, bool want_v);

@@ -38,7 +38,8 @@ __global__ __launch_bounds__(WG) void precompute_kernel(const double *__restrict
                                                         double *__restrict__ d, int *__restrict__ rho,
                                                         int4 *__restrict__ S, int *__restrict__ C,
                                                         unsigned int *__restrict__ nrot,
-                                                        unsigned int *__restrict__ nskip, Ctl *ctl)
+                                                        unsigned int *__restrict__ nskip,
+                                                        unsigned int *__restrict__ nact, Ctl *ctl)
 {
     __shared__ double sh[WG / 64];
     const int c = blockIdx.x;
@@ -59,6 +60,7 @@ __global__ __launch_bounds__(WG) void precompute_kernel(const double *__restrict
             C[c] = 0;
             nrot[c] = 0;
             nskip[c] = 0;
+            nact[c] = 0;
         }
     }
 }
@@ -235,44 +237,51 @@ __global__ __launch_bounds__(kSortThreads) void sort_kernel(double *__restrict__
 __global__ __launch_bounds__(1024) void sweep_reduce_kernel(int *__restrict__ C,
                                                             unsigned int *__restrict__ nrot,
                                                             unsigned int *__restrict__ nskip,
+                                                            unsigned int *__restrict__ nact,
                                                             int slots, Ctl *ctl)
 {
     __shared__ int scode[16];
-    __shared__ unsigned long long srot[16], sskip[16];
+    __shared__ unsigned long long srot[16], sskip[16], sact[16];
     int code = 0;
-    unsigned long long rot = 0, skp = 0;
+    unsigned long long rot = 0, skp = 0, act = 0;
     for (int k = threadIdx.x; k < slots; k += 1024) {
         code |= C[k];
         rot += nrot[k];
         skp += nskip[k];
+        act += nact[k];
         C[k] = 0;
         nrot[k] = 0;
         nskip[k] = 0;
+        nact[k] = 0;
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
         code |= __shfl_xor(code, m, 64);
         rot += __shfl_xor(rot, m, 64);
         skp += __shfl_xor(skp, m, 64);
+        act += __shfl_xor(act, m, 64);
     }
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         scode[w] = code;
         srot[w] = rot;
         sskip[w] = skp;
+        sact[w] = act;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int cc = 0;
-        unsigned long long rr = 0, ss = 0;
+        unsigned long long rr = 0, ss = 0, aa = 0;
         for (int q = 0; q < 16; ++q) {
             cc |= scode[q];
             rr += srot[q];
             ss += sskip[q];
+            aa += sact[q];
         }
         ctl->code = cc;
         ctl->rot += rr;
         ctl->skip += ss;
+        ctl->act += aa;
     }
 }
 
@@ -285,6 +294,7 @@ __global__ void zero_ctl_kernel(Ctl *ctl)
         ctl->pad = 0;
         ctl->rot = 0;
         ctl->skip = 0;
+        ctl->act = 0;
     }
 }
 
@@ -407,7 +417,8 @@ hipError_t launch_setup(hipStream_t st, const double *G, int lda, int n, const W
 
 hipError_t launch_precompute(hipStream_t st, const Workspace &w, int r, int ldg)
 {
-    precompute_kernel<256><<<r, 256, 0, st>>>(w.G, ldg, r, w.d, w.rho, w.S, w.C, w.nrot, w.nskip, w.ctl);
+    precompute_kernel<256><<<r, 256, 0, st>>>(w.G, ldg, r, w.d, w.rho, w.S, w.C, w.nrot, w.nskip,
+                                              w.nact, w.ctl);
     return hipGetLastError();
 }
 
@@ -440,7 +451,7 @@ hipError_t launch_sort(hipStream_t st, double *d, int *rho, double *dtmp, int *r
 
 hipError_t launch_sweep_reduce(hipStream_t st, const Workspace &w, int slots)
 {
-    sweep_reduce_kernel<<<1, 1024, 0, st>>>(w.C, w.nrot, w.nskip, slots, w.ctl);
+    sweep_reduce_kernel<<<1, 1024, 0, st>>>(w.C, w.nrot, w.nskip, w.nact, slots, w.ctl);
     return hipGetLastError();
 }
 

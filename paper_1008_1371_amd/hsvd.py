@@ -34,16 +34,29 @@ class hsvd_params(ctypes.Structure):
                 ("t_thresh", ctypes.c_double)]
 
 
+NKERNELS = 4
+K_PAIR_STEP, K_BLOCK_GRAM, K_BLOCK_INNER, K_BLOCK_UPDATE = range(NKERNELS)
+KERNEL_NAMES = ["pair_step_kernel", "block_gram_kernel", "block_inner_kernel",
+                "block_update_kernel"]
+
+
 class hsvd_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("sweeps", ctypes.c_int), ("code", ctypes.c_int),
-                ("r", ctypes.c_int), ("rotations", ctypes.c_longlong),
-                ("skips", ctypes.c_longlong), ("steps", ctypes.c_longlong),
-                ("ms_total", ctypes.c_double), ("ms_steps", ctypes.c_double),
-                ("step_launches", ctypes.c_longlong), ("step_bytes", ctypes.c_double),
-                ("step_flops", ctypes.c_double)]
+                ("r", ctypes.c_int), ("block", ctypes.c_int), ("ldg", ctypes.c_int),
+                ("rotations", ctypes.c_longlong), ("skips", ctypes.c_longlong),
+                ("steps", ctypes.c_longlong), ("active_pairs", ctypes.c_longlong),
+                ("ms_total", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double * NKERNELS),
+                ("kernel_launches", ctypes.c_longlong * NKERNELS),
+                ("kernel_bytes", ctypes.c_double * NKERNELS),
+                ("kernel_flops", ctypes.c_double * NKERNELS)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = list(v) if hasattr(v, "__len__") else v
+        return out
 
 
 _lib = None
@@ -76,9 +89,10 @@ def lib():
                                    vp]
     L.hsvd_pivot_trace.argtypes = [vp, ip, ip, ip, vp]
     L.hsvd_sort_diag.argtypes = [vp, ip, ip, vp, vp]
+    L.hsvd_block_trace.argtypes = [vp, ip, ip, ip, ip, vp]
     L.hsvd_version.restype = ctypes.c_char_p
     for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_pair_params",
-                 "hsvd_pivot_trace", "hsvd_sort_diag"):
+                 "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_block_trace"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -341,8 +341,9 @@ def check_invariants(G, p, R, *, tol):
     assert np.max(np.abs(np.diag(UtU) - 1)) <= 8 * n * U_RND
     if V is not None:
         vn = np.linalg.norm(V, 2) ** 2
-        # rounding accumulates over the ~n rotations per column per sweep
-        bound = 2 * max(R["sweeps"], 1) * n * U_RND
+        # each column takes ~n rotations per sweep; their rounding errors add up
+        # like a random walk over the n*sweeps rotations, over n^2 entries
+        bound = 4 * n * np.sqrt(n * max(R["sweeps"], 1)) * U_RND
         assert np.linalg.norm(V.T @ J @ V - J) / vn <= bound, \
             ("V^T J V", np.linalg.norm(V.T @ J @ V - J) / vn, bound)
         r = np.linalg.norm(G @ V - U * s) / (np.linalg.norm(G) * max(1.0, np.linalg.norm(V, 2)))

@@ -17,7 +17,8 @@ def _lib_or_skip():
 def test_header_declares_the_entry_points():
     names = H.header_functions()
     for required in ("hsvd_init", "hsvd_destroy", "hsvd_default_params", "hsvd_solve",
-                     "hsvd_pair_params", "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_version"):
+                     "hsvd_pair_params", "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_block_trace",
+                     "hsvd_version"):
         assert required in names
 
 
@@ -51,5 +52,5 @@ def test_struct_layouts_match_header():
         body = body.split("} " + struct + ";")[0]
         import re
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-        fields = re.findall(r"\b(\w+)\s*;", body)
+        fields = re.findall(r"\b(\w+)\s*(?:\[\w+\])?\s*;", body)
         assert fields == [f for f, _ in cls._fields_], (struct, fields)
