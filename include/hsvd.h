@@ -44,7 +44,9 @@ typedef enum { HSVD_AUTO = 0, HSVD_PAIRWISE = 1, HSVD_BLOCK = 2 } hsvd_algo;
 typedef enum { HSVD_ORD_MODMOD = 0, HSVD_ORD_ROUNDROBIN = 1 } hsvd_ordering;
 
 typedef struct {
-    int precision;   /* hsvd_precision; HSVD_FP64 is the pairwise / block FP64 path     */
+    int precision;   /* hsvd_precision: HSVD_FP64, or HSVD_MIXED = FP32 block sweeps on
+                        FP32 MFMA until the largest tangent stagnates, FP64
+                        J-re-orthogonalisation of V, then FP64 block sweeps          */
     int algo;        /* hsvd_algo                                                        */
     int ordering;    /* hsvd_ordering: modified modulus (Sec. 2, Algs. 4.3-4.4) or the
                         round-robin circle method starting on the same antidiagonal      */
@@ -58,11 +60,15 @@ typedef struct {
 
 /* Kernel classes timed in hsvd_info (index into the kernel_* arrays). */
 enum {
-    HSVD_K_PAIR_STEP = 0,    /* pairwise path: one parallel step of pivot pairs            */
-    HSVD_K_BLOCK_GRAM = 1,   /* block path: Gram matrices G_P^T G_P of the block pairs      */
-    HSVD_K_BLOCK_INNER = 2,  /* block path: inner rotations of each block pair             */
-    HSVD_K_BLOCK_UPDATE = 3, /* block path: [G_P | V_P] <- [G_P | V_P] W                   */
-    HSVD_NKERNELS = 4
+    HSVD_K_PAIR_STEP = 0,      /* pairwise path: one parallel step of pivot pairs          */
+    HSVD_K_BLOCK_GRAM = 1,     /* block path, FP64: Gram matrices G_P^T G_P                */
+    HSVD_K_BLOCK_INNER = 2,    /* block path, FP64: inner rotations of each block pair     */
+    HSVD_K_BLOCK_UPDATE = 3,   /* block path, FP64: [G_P | V_P] <- [G_P | V_P] W           */
+    HSVD_K_BLOCK_GRAM32 = 4,   /* mixed path, FP32 sweeps: Gram on FP32 MFMA               */
+    HSVD_K_BLOCK_INNER32 = 5,  /* mixed path, FP32 sweeps: inner rotations (FP64)          */
+    HSVD_K_BLOCK_UPDATE32 = 6, /* mixed path, FP32 sweeps: update on FP32 MFMA             */
+    HSVD_K_REORTH = 7,         /* mixed path: J-re-orthogonalisation of V and G1 = G X     */
+    HSVD_NKERNELS = 8
 };
 
 typedef struct {
@@ -72,6 +78,10 @@ typedef struct {
     int r;                   /* bordered order (eq. 4.1)                                 */
     int block;               /* block width b used; 0 = pairwise path                    */
     int ldg;                 /* padded leading dimension of the working copies           */
+    int sweeps_fp32;         /* mixed path: FP32 sweeps before the FP64 refinement       */
+    int reorth_iters;        /* mixed path: Newton-Schulz iterations on V                */
+    double max_t_last;       /* largest |t| of the last sweep                            */
+    double reorth_resid;     /* mixed path: final max |J X^T J X - I|                    */
     long long rotations;     /* rotations applied                                        */
     long long skips;         /* pair visits skipped by eq. (2.3)                         */
     long long steps;         /* parallel (outer) steps executed                          */
@@ -112,6 +122,28 @@ void hsvd_default_params(hsvd_params *prm);
 hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p,
                        const hsvd_params *prm, double *sigma, double *U, int ldu,
                        double *V, int ldv, double *lambda, int *perm, hsvd_info *info);
+
+/* Batched solves: `batch` independent problems G_k (n[k] x n[k], 1 <= n[k] <= 1024,
+ * J_k = diag(I_p[k], -I_{n[k]-p[k]})), each solved as by hsvd_solve with the block
+ * path (FP64) and its own tolerance (prm->tol <= 0: 1e-15 n[k]) and stop rule.
+ *   n, p, off, voff  host arrays of `batch` entries: order, number of +1 signs,
+ *                    element offset of G_k / U_k / V_k in the packed matrices
+ *                    (column-major, leading dimension n[k]), element offset of
+ *                    sigma_k / lambda_k in the packed vectors.
+ *   G                device, packed inputs (read only).
+ *   sigma, U, V, lambda  device, packed outputs (U, V, lambda may be NULL;
+ *                    V requires prm->want_v).
+ *   status, sweeps   host arrays of `batch` ints (may be NULL): each problem's
+ *                    hsvd_status and sweep count.
+ *   info             host, may be NULL: totals over the batch (sweeps = largest).
+ * Problems are grouped by their bordered order (a multiple of 2b); each group
+ * runs as one sequence of launches that covers all of its problems.  Returns
+ * HSVD_OK when every problem converged, else the status of the first problem
+ * that did not.  Synchronises. */
+hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n, const int *p, const long long *off,
+                               const long long *voff, const double *G, const hsvd_params *prm, double *sigma,
+                               double *U, double *V, double *lambda, int *status, int *sweeps,
+                               hsvd_info *info);
 
 /* ---- Diagnostics: the individual steps of the path on caller data ---- */
 

@@ -12,6 +12,8 @@
 #include <new>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "internal.h"
 
 struct hsvd_ctx {
@@ -21,13 +23,14 @@ struct hsvd_ctx {
     size_t ws_bytes = 0;
     hsvd::Ctl *host_ctl = nullptr;           // pinned
     std::vector<hipEvent_t> events;          // reusable timing events
+    rocblas_handle blas = nullptr;           // created on the first mixed solve
 };
 
 namespace hsvd {
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-Layout make_layout(int n, int r, int ldg, bool want_v, int pairs, int splits, int b2)
+Layout make_layout(int n, int r, int ldg, bool want_v, int pairs, int splits, int b2, bool mixed)
 {
     Layout L;
     L.n = n;
@@ -54,12 +57,21 @@ Layout make_layout(int n, int r, int ldg, bool want_v, int pairs, int splits, in
     L.off_nrot = take(sizeof(unsigned int) * slots);
     L.off_nskip = take(sizeof(unsigned int) * slots);
     L.off_nact = take(sizeof(unsigned int) * slots);
+    L.off_maxt = take(sizeof(double) * slots);
     L.off_ctl = take(sizeof(Ctl));
     const size_t bb = (size_t)b2 * b2;
     L.off_P = take(sizeof(double) * (size_t)pairs * splits * bb);
     L.off_W = take(sizeof(double) * (size_t)pairs * bb);
     L.off_active = take(sizeof(int) * (size_t)pairs);
     L.off_S2 = take(sizeof(int4) * 2 * (size_t)pairs);
+    L.mixed = mixed;
+    const size_t mat = (size_t)ldg * r;
+    L.off_G32 = take(mixed ? sizeof(float) * mat : 0);
+    L.off_V32 = take(mixed && want_v ? sizeof(float) * mat : 0);
+    L.off_P32 = take(mixed ? sizeof(float) * (size_t)pairs * splits * bb : 0);
+    L.off_W32 = take(mixed ? sizeof(float) * (size_t)pairs * bb : 0);
+    L.off_T1 = take(mixed && want_v ? sizeof(double) * mat : 0);
+    L.off_T2 = take(mixed && want_v ? sizeof(double) * mat : 0);
     L.bytes = o;
     return L;
 }
@@ -79,12 +91,21 @@ Workspace carve(void *base, const Layout &L)
     w.nrot = reinterpret_cast<unsigned int *>(b + L.off_nrot);
     w.nskip = reinterpret_cast<unsigned int *>(b + L.off_nskip);
     w.nact = reinterpret_cast<unsigned int *>(b + L.off_nact);
+    w.maxt = reinterpret_cast<double *>(b + L.off_maxt);
     w.ctl = reinterpret_cast<Ctl *>(b + L.off_ctl);
     if (L.pairs > 0) {
         w.P = reinterpret_cast<double *>(b + L.off_P);
         w.W = reinterpret_cast<double *>(b + L.off_W);
         w.active = reinterpret_cast<int *>(b + L.off_active);
         w.S2 = reinterpret_cast<int4 *>(b + L.off_S2);
+    }
+    if (L.mixed) {
+        w.G32 = reinterpret_cast<float *>(b + L.off_G32);
+        w.V32 = L.off_P32 > L.off_V32 ? reinterpret_cast<float *>(b + L.off_V32) : nullptr;
+        w.P32 = reinterpret_cast<float *>(b + L.off_P32);
+        w.W32 = reinterpret_cast<float *>(b + L.off_W32);
+        w.T1 = L.off_T2 > L.off_T1 ? reinterpret_cast<double *>(b + L.off_T1) : nullptr;
+        w.T2 = L.bytes > L.off_T2 ? reinterpret_cast<double *>(b + L.off_T2) : nullptr;
     }
     return w;
 }
@@ -173,9 +194,124 @@ hsvd_status hsvd_destroy(hsvd_ctx *ctx)
     for (hipEvent_t e : ctx->events) hipEventDestroy(e);
     if (ctx->ws) hipFree(ctx->ws);
     if (ctx->host_ctl) hipHostFree(ctx->host_ctl);
+    if (ctx->blas) rocblas_destroy_handle(ctx->blas);
     delete ctx;
     return HSVD_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Outcome of one sweep, read back from the control block.
+struct SweepResult {
+    int code;
+    double maxt;
+    bool rank;
+};
+
+// Runs block sweeps of storage type T until `done(sweep_result)` says so or
+// max_sweeps is reached.  Kernel times go to kms[kbase + 0..2] (Gram, inner,
+// update).  Returns HSVD_OK, HSVD_E_RANK or HSVD_E_DEVICE; *finished tells
+// whether `done` accepted a sweep.
+template <typename T, typename Done>
+hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, const T *Gcur, int pairs,
+                         int steps_per_sweep, int max_sweeps, bool sort, int r, int p, int ldg, long long &gstep,
+                         int kbase, double *kms, long long *klaunch, int &sweeps, long long &steps,
+                         SweepResult &last, bool &finished, Done done)
+{
+    hipStream_t st = ctx->stream;
+    hipEvent_t *ev = ctx->events.data();
+    finished = false;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+        for (int k = 0; k < steps_per_sweep; ++k, ++gstep) {
+            ba.step = k;
+            ba.S_in = w.S2 + (gstep & 1) * pairs;
+            ba.S_out = w.S2 + ((gstep + 1) & 1) * pairs;
+            hipEvent_t *e = ev + 4 + 4 * k;
+            HSVD_TRY(hipEventRecord(e[0], st));
+            HSVD_TRY(launch_block_gram<T>(st, ba));
+            HSVD_TRY(hipEventRecord(e[1], st));
+            HSVD_TRY(launch_block_inner<T>(st, ba));
+            HSVD_TRY(hipEventRecord(e[2], st));
+            HSVD_TRY(launch_block_update<T>(st, ba));
+            HSVD_TRY(hipEventRecord(e[3], st));
+        }
+        for (int q = 0; q < 3; ++q) klaunch[kbase + q] += steps_per_sweep;
+        // the kept diagonal: fresh column norms of the updated columns
+        HSVD_TRY(launch_colnorm_pos<T>(st, Gcur, ldg, w.rho, w.d, r));
+        steps += steps_per_sweep;
+        if (sort) HSVD_TRY(launch_sort(st, w.d, w.rho, w.dtmp, w.rtmp, r, p));
+        HSVD_TRY(launch_sweep_reduce(st, w, pairs));
+        HSVD_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HSVD_TRY(hipStreamSynchronize(st));
+        for (int k = 0; k < steps_per_sweep; ++k) {
+            hipEvent_t *e = ev + 4 + 4 * k;
+            for (int q = 0; q < 3; ++q) {
+                float ms = 0.f;
+                HSVD_TRY(hipEventElapsedTime(&ms, e[q], e[q + 1]));
+                kms[kbase + q] += ms;
+            }
+        }
+        ++sweeps;
+        last.code = ctx->host_ctl->code;
+        last.maxt = ctx->host_ctl->maxt;
+        last.rank = ctx->host_ctl->rank != 0;
+        if (last.rank) return HSVD_E_RANK;
+        if (done(last)) {
+            finished = true;
+            break;
+        }
+    }
+    return HSVD_OK;
+}
+
+#define BLAS_TRY(expr)                                          \
+    do {                                                        \
+        if ((expr) != rocblas_status_success) return HSVD_E_DEVICE; \
+    } while (0)
+
+// Newton-Schulz J-re-orthogonalisation of X (in w.V, FP64, promoted from the
+// FP32 sweeps) followed by G <- G X.  Uses w.T1, w.T2.
+hsvd_status reorthogonalise(hsvd_ctx *ctx, const Workspace &w, int r, int p, int ldg, int &iters, double &resid)
+{
+    hipStream_t st = ctx->stream;
+    if (!ctx->blas) {
+        if (rocblas_create_handle(&ctx->blas) != rocblas_status_success) return HSVD_E_DEVICE;
+    }
+    BLAS_TRY(rocblas_set_stream(ctx->blas, st));
+    const double one = 1.0, zero = 0.0;
+    iters = 0;
+    resid = 1.0;
+    double prev = 2.0;
+    for (int it = 0; it < 6; ++it) {
+        HSVD_TRY(launch_rowsign(st, w.V, w.T1, p, ldg, r));  // T1 = J X
+        BLAS_TRY(rocblas_dgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, r, r, r, &one, w.V,
+                               ldg, w.T1, ldg, &zero, w.T2, ldg));  // T2 = X^T J X
+        ctx->host_ctl->nsres = 0.0;
+        HSVD_TRY(hipMemcpyAsync(&w.ctl->nsres, &ctx->host_ctl->nsres, sizeof(double), hipMemcpyHostToDevice, st));
+        HSVD_TRY(launch_ns_form(st, w.T2, p, ldg, r, w.ctl));  // T2 = (3I - J X^T J X) / 2
+        HSVD_TRY(hipMemcpyAsync(&ctx->host_ctl->nsres, &w.ctl->nsres, sizeof(double), hipMemcpyDeviceToHost, st));
+        HSVD_TRY(hipStreamSynchronize(st));
+        resid = ctx->host_ctl->nsres;
+        // stop once X is J-orthogonal to working accuracy (the residual no
+        // longer falls quadratically) -- the last correction is not applied
+        if (!(resid < 1.0) || (iters > 0 && resid > 0.25 * prev)) break;
+        BLAS_TRY(rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, r, r, r, &one, w.V, ldg,
+                               w.T2, ldg, &zero, w.T1, ldg));  // T1 = X T2
+        HSVD_TRY(launch_copy(st, w.T1, w.V, ldg, r));
+        ++iters;
+        prev = resid;
+    }
+    BLAS_TRY(rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, r, r, r, &one, w.G, ldg,
+                           w.V, ldg, &zero, w.T1, ldg));  // T1 = G X
+    HSVD_TRY(launch_copy(st, w.T1, w.G, ldg, r));
+    return HSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, const hsvd_params *prm_in,
                        double *sigma, double *U, int ldu, double *V, int ldv, double *lambda, int *perm,
@@ -190,12 +326,15 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
     if (U && ldu < n) return HSVD_E_INVAL;
     if (V && ldv < n) return HSVD_E_INVAL;
     if (prm.ordering != HSVD_ORD_MODMOD && prm.ordering != HSVD_ORD_ROUNDROBIN) return HSVD_E_INVAL;
-    if (prm.precision != HSVD_FP64) return HSVD_E_INVAL;
+    if (prm.precision != HSVD_FP64 && prm.precision != HSVD_MIXED) return HSVD_E_INVAL;
     if (prm.algo != HSVD_AUTO && prm.algo != HSVD_PAIRWISE && prm.algo != HSVD_BLOCK) return HSVD_E_INVAL;
     if (prm.block != 0 && prm.block != block_width()) return HSVD_E_INVAL;
     if (V && !prm.want_v) return HSVD_E_INVAL;
-    // The block path needs at least two blocks of b columns; AUTO takes it from n >= 512.
-    const bool block = prm.algo == HSVD_BLOCK || (prm.algo == HSVD_AUTO && n >= 512);
+    const bool mixed = prm.precision == HSVD_MIXED;
+    if (mixed && prm.algo == HSVD_PAIRWISE) return HSVD_E_INVAL;
+    // The block path needs at least two blocks of b columns; AUTO takes it from
+    // n >= 512, and always for the mixed path.
+    const bool block = mixed || prm.algo == HSVD_BLOCK || (prm.algo == HSVD_AUTO && n >= 512);
     const int b = block ? block_width() : 0;
     const int mult = block ? 2 * b : 2;
     const int r = (n + mult - 1) / mult * mult;  // eq. (4.1) bordering
@@ -215,6 +354,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
         const int chunks = ldg / 64;
         int want = (1024 + pairs - 1) / pairs;
         want = want < 1 ? 1 : (want > chunks ? chunks : want);
+        if (want > 32) want = 32;  // the inner kernels sum at most 32 partial Grams
         rows_per_split = (chunks + want - 1) / want * 64;
         splits = (ldg + rows_per_split - 1) / rows_per_split;
     }
@@ -222,7 +362,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
                                       : (prm.ordering == HSVD_ORD_MODMOD ? r : r - 1);
 
     HSVD_TRY(hipSetDevice(ctx->device));
-    const Layout L = make_layout(n, r, ldg, want_v, pairs, splits, block ? 2 * b : 0);
+    const Layout L = make_layout(n, r, ldg, want_v, pairs, splits, block ? 2 * b : 0, mixed);
     hsvd_status s = ensure_ws(ctx, L.bytes);
     if (s != HSVD_OK) return s;
     const int nev = block ? 4 + 4 * steps_per_sweep : 4;
@@ -242,104 +382,53 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
     HSVD_TRY(hipStreamSynchronize(st));
 
     hsvd_status status = HSVD_OK;
-    int sweeps = 0, code = 0;
+    int sweeps = 0, sweeps32 = 0, code = 0, ns_iters = 0;
+    double maxt_last = 0.0, ns_resid = 0.0;
     long long steps = 0;
-    double kms[HSVD_NKERNELS] = {0, 0, 0, 0};
-    long long klaunch[HSVD_NKERNELS] = {0, 0, 0, 0};
+    double kms[HSVD_NKERNELS] = {0};
+    long long klaunch[HSVD_NKERNELS] = {0};
     if (ctx->host_ctl->inval) status = HSVD_E_INVAL;
     else if (ctx->host_ctl->rank) status = HSVD_E_RANK;
 
-    StepArgs a;
-    a.G = w.G;
-    a.V = want_v ? w.V : nullptr;
-    a.ldg = ldg;
-    a.r = r;
-    a.p = p;
-    a.d = w.d;
-    a.rho = w.rho;
-    a.S = w.S;
-    a.C = w.C;
-    a.nrot = w.nrot;
-    a.nskip = w.nskip;
-    a.ctl = w.ctl;
-    a.ordering = prm.ordering;
-    a.tol = tol;
-    a.tthresh = tthresh;
-
-    BlockArgs ba;
-    ba.G = w.G;
-    ba.V = want_v ? w.V : nullptr;
-    ba.ldg = ldg;
-    ba.r = r;
-    ba.p = p;
-    ba.nb = nb;
-    ba.rho = w.rho;
-    ba.ordering = prm.ordering;
-    ba.partial = w.P;
-    ba.splits = splits;
-    ba.rows_per_split = rows_per_split;
-    ba.W = w.W;
-    ba.active = w.active;
-    ba.C = w.C;
-    ba.nrot = w.nrot;
-    ba.nskip = w.nskip;
-    ba.nact = w.nact;
-    ba.ctl = w.ctl;
-    ba.tol = tol;
-    ba.tthresh = tthresh;
-
     bool converged = false;
     long long gstep = 0;
-    if (status == HSVD_OK) {
+    if (status == HSVD_OK && !block) {
+        StepArgs a;
+        a.G = w.G;
+        a.V = want_v ? w.V : nullptr;
+        a.ldg = ldg;
+        a.r = r;
+        a.p = p;
+        a.d = w.d;
+        a.rho = w.rho;
+        a.S = w.S;
+        a.C = w.C;
+        a.nrot = w.nrot;
+        a.nskip = w.nskip;
+        a.maxt = w.maxt;
+        a.ctl = w.ctl;
+        a.ordering = prm.ordering;
+        a.tol = tol;
+        a.tthresh = tthresh;
         for (int sw = 0; sw < max_sweeps; ++sw) {
-            if (!block) {
-                HSVD_TRY(hipEventRecord(ev[2], st));
-                for (int k = 0; k < steps_per_sweep; ++k) {
-                    a.step = k;
-                    HSVD_TRY(launch_pair_step(st, a));
-                }
-                HSVD_TRY(hipEventRecord(ev[3], st));
-                klaunch[HSVD_K_PAIR_STEP] += steps_per_sweep;
-            } else {
-                for (int k = 0; k < steps_per_sweep; ++k, ++gstep) {
-                    ba.step = k;
-                    ba.S_in = w.S2 + (gstep & 1) * pairs;
-                    ba.S_out = w.S2 + ((gstep + 1) & 1) * pairs;
-                    hipEvent_t *e = ev + 4 + 4 * k;
-                    HSVD_TRY(hipEventRecord(e[0], st));
-                    HSVD_TRY(launch_block_gram(st, ba));
-                    HSVD_TRY(hipEventRecord(e[1], st));
-                    HSVD_TRY(launch_block_inner(st, ba));
-                    HSVD_TRY(hipEventRecord(e[2], st));
-                    HSVD_TRY(launch_block_update(st, ba));
-                    HSVD_TRY(hipEventRecord(e[3], st));
-                }
-                klaunch[HSVD_K_BLOCK_GRAM] += steps_per_sweep;
-                klaunch[HSVD_K_BLOCK_INNER] += steps_per_sweep;
-                klaunch[HSVD_K_BLOCK_UPDATE] += steps_per_sweep;
-                // the kept diagonal: fresh column norms of the updated columns
-                HSVD_TRY(launch_colnorm_pos(st, w.G, ldg, w.rho, w.d, r));
+            HSVD_TRY(hipEventRecord(ev[2], st));
+            for (int k = 0; k < steps_per_sweep; ++k) {
+                a.step = k;
+                HSVD_TRY(launch_pair_step(st, a));
             }
+            HSVD_TRY(hipEventRecord(ev[3], st));
+            klaunch[HSVD_K_PAIR_STEP] += steps_per_sweep;
             steps += steps_per_sweep;
             if (prm.sort) HSVD_TRY(launch_sort(st, w.d, w.rho, w.dtmp, w.rtmp, r, p));
-            HSVD_TRY(launch_sweep_reduce(st, w, block ? pairs : r / 2));
+            HSVD_TRY(launch_sweep_reduce(st, w, r / 2));
             HSVD_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
             HSVD_TRY(hipStreamSynchronize(st));
             float ms = 0.f;
-            if (!block) {
-                HSVD_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
-                kms[HSVD_K_PAIR_STEP] += ms;
-            } else {
-                for (int k = 0; k < steps_per_sweep; ++k) {
-                    hipEvent_t *e = ev + 4 + 4 * k;
-                    for (int q = 0; q < 3; ++q) {
-                        HSVD_TRY(hipEventElapsedTime(&ms, e[q], e[q + 1]));
-                        kms[HSVD_K_BLOCK_GRAM + q] += ms;
-                    }
-                }
-            }
+            HSVD_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
+            kms[HSVD_K_PAIR_STEP] += ms;
             ++sweeps;
             code = ctx->host_ctl->code;
+            maxt_last = ctx->host_ctl->maxt;
             if (ctx->host_ctl->rank) {
                 status = HSVD_E_RANK;
                 break;
@@ -350,6 +439,103 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             }
         }
         if (status == HSVD_OK && !converged) status = HSVD_E_NOCONV;
+    } else if (status == HSVD_OK) {
+        SweepResult last = {0, 0.0, false};
+        bool finished = false;
+        if (mixed) {
+            // FP32 sweeps on FP32 copies of G and V.
+            HSVD_TRY(launch_to_fp32(st, w.G, w.G32, want_v ? w.V32 : nullptr, ldg, r));
+            BlockArgsT<float> fa;
+            fa.G = w.G32;
+            fa.V = want_v ? w.V32 : nullptr;
+            fa.ldg = ldg;
+            fa.r = r;
+            fa.p = p;
+            fa.nb = nb;
+            fa.rho = w.rho;
+            fa.ordering = prm.ordering;
+            fa.partial = w.P32;
+            fa.splits = splits;
+            fa.rows_per_split = rows_per_split;
+            fa.W = w.W32;
+            fa.active = w.active;
+            fa.C = w.C;
+            fa.nrot = w.nrot;
+            fa.nskip = w.nskip;
+            fa.nact = w.nact;
+            fa.maxt = w.maxt;
+            fa.ctl = w.ctl;
+            // the FP32 Gram resolves cosines down to about sqrt(r) FP32 epsilons
+            const double tol32 = fmax(tol, sqrt((double)r) * 0x1p-23);
+            fa.tol = tol32;
+            fa.tthresh = sqrt(tol32) / 2.0;
+            double prev = 1.0;
+            int sw32 = 0;
+            // Leave FP32 when the largest tangent of a sweep is at the FP32
+            // resolution (<= 3e-4 ~ sqrt(eps32)), when it stagnates (falls by
+            // less than 4x once below 0.1), or when FP32 itself converged.
+            auto done32 = [&](const SweepResult &sr) {
+                const bool stop = sr.maxt <= 3e-4 || (sr.code & 2) == 0 || (sr.maxt < 0.1 && sr.maxt > 0.25 * prev);
+                prev = sr.maxt;
+                return stop;
+            };
+            status = block_sweeps<float>(ctx, w, fa, w.G32, pairs, steps_per_sweep, max_sweeps, prm.sort != 0, r,
+                                         p, ldg, gstep, HSVD_K_BLOCK_GRAM32, kms, klaunch, sw32, steps, last,
+                                         finished, done32);
+            sweeps32 = sw32;
+            if (status == HSVD_OK) {
+                // back to FP64: X = J-orthogonalised V32, G1 = G X, V0 = X
+                HSVD_TRY(hipEventRecord(ev[2], st));
+                if (want_v) {
+                    HSVD_TRY(launch_promote(st, w.V32, w.V, ldg, r));
+                    s = reorthogonalise(ctx, w, r, p, ldg, ns_iters, ns_resid);
+                    if (s != HSVD_OK) return s;
+                } else {
+                    // without V the FP32 phase only serves as a preconditioner of G
+                    HSVD_TRY(launch_promote(st, w.G32, w.G, ldg, r));
+                }
+                HSVD_TRY(hipEventRecord(ev[3], st));
+                HSVD_TRY(hipStreamSynchronize(st));
+                float ms = 0.f;
+                HSVD_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
+                kms[HSVD_K_REORTH] += ms;
+                klaunch[HSVD_K_REORTH] += 1;
+                HSVD_TRY(launch_colnorm_pos<double>(st, w.G, ldg, w.rho, w.d, r));
+                if (prm.sort) HSVD_TRY(launch_sort(st, w.d, w.rho, w.dtmp, w.rtmp, r, p));
+            }
+        }
+        if (status == HSVD_OK) {
+            BlockArgs ba;
+            ba.G = w.G;
+            ba.V = want_v ? w.V : nullptr;
+            ba.ldg = ldg;
+            ba.r = r;
+            ba.p = p;
+            ba.nb = nb;
+            ba.rho = w.rho;
+            ba.ordering = prm.ordering;
+            ba.partial = w.P;
+            ba.splits = splits;
+            ba.rows_per_split = rows_per_split;
+            ba.W = w.W;
+            ba.active = w.active;
+            ba.C = w.C;
+            ba.nrot = w.nrot;
+            ba.nskip = w.nskip;
+            ba.nact = w.nact;
+            ba.maxt = w.maxt;
+            ba.ctl = w.ctl;
+            ba.tol = tol;
+            ba.tthresh = tthresh;
+            auto done64 = [](const SweepResult &sr) { return (sr.code & 2) == 0; };  // eq. (4.2)
+            status = block_sweeps<double>(ctx, w, ba, w.G, pairs, steps_per_sweep, max_sweeps, prm.sort != 0, r, p,
+                                          ldg, gstep, HSVD_K_BLOCK_GRAM, kms, klaunch, sweeps, steps, last,
+                                          finished, done64);
+            code = last.code;
+            maxt_last = last.maxt;
+            if (status == HSVD_OK && !finished) status = HSVD_E_NOCONV;
+        }
+        if (status == HSVD_E_DEVICE) return status;
     }
 
     HSVD_TRY(launch_finalize(st, w, n, r, p, ldg, sigma, U, ldu, V, ldv, lambda, perm));
@@ -360,6 +546,10 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
         hipEventElapsedTime(&ms, ev[0], ev[1]);
         info->status = status;
         info->sweeps = sweeps;
+        info->sweeps_fp32 = sweeps32;
+        info->reorth_iters = ns_iters;
+        info->reorth_resid = ns_resid;
+        info->max_t_last = maxt_last;
         info->code = code;
         info->r = r;
         info->block = b;
@@ -385,20 +575,298 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
         } else {
             // per block pair and step: the Gram reads 2b columns and does a full
             // (2b)^2 x rows product; an active pair's update reads and writes the
-            // 2b columns of G (and of V) with (2b)^2 x rows multiply-adds each
+            // 2b columns of G (and of V) with (2b)^2 x rows multiply-adds each.
+            // Active pair steps are not split by precision: the update figures
+            // use the share of steps each precision ran.
             const double b2 = 2.0 * b;
-            const double visits = (double)steps * pairs;
             const double act = (double)info->active_pairs;
-            info->kernel_bytes[HSVD_K_BLOCK_GRAM] = visits * 8.0 * b2 * rows;
-            info->kernel_flops[HSVD_K_BLOCK_GRAM] = visits * 2.0 * b2 * b2 * rows;
-            info->kernel_bytes[HSVD_K_BLOCK_UPDATE] = act * 16.0 * b2 * rows * vmul;
-            info->kernel_flops[HSVD_K_BLOCK_UPDATE] = act * 2.0 * b2 * b2 * rows * vmul;
-            info->kernel_bytes[HSVD_K_BLOCK_INNER] = visits * (double)(splits + 1) * 8.0 * b2 * b2;
-            info->kernel_flops[HSVD_K_BLOCK_INNER] = 0.0;
+            const double st64 = (double)klaunch[HSVD_K_BLOCK_GRAM], st32 = (double)klaunch[HSVD_K_BLOCK_GRAM32];
+            const double frac64 = (st64 + st32) > 0 ? st64 / (st64 + st32) : 1.0;
+            for (int prec = 0; prec < 2; ++prec) {
+                const int kb = prec == 0 ? HSVD_K_BLOCK_GRAM : HSVD_K_BLOCK_GRAM32;
+                const double esz = prec == 0 ? 8.0 : 4.0;
+                const double visits = (prec == 0 ? st64 : st32) * pairs;
+                const double acts = act * (prec == 0 ? frac64 : 1.0 - frac64);
+                info->kernel_bytes[kb] = visits * esz * b2 * rows;
+                info->kernel_flops[kb] = visits * 2.0 * b2 * b2 * rows;
+                info->kernel_bytes[kb + 1] = visits * (double)(splits * esz + 2 * esz) * b2 * b2;
+                info->kernel_flops[kb + 1] = 0.0;
+                info->kernel_bytes[kb + 2] = acts * 2.0 * esz * b2 * rows * vmul;
+                info->kernel_flops[kb + 2] = acts * 2.0 * b2 * b2 * rows * vmul;
+            }
+            if (mixed && want_v) {
+                const double rr = (double)r;
+                info->kernel_flops[HSVD_K_REORTH] = (2.0 * ns_iters + 1.0 + 1.0) * 2.0 * rr * rr * rr;
+                info->kernel_bytes[HSVD_K_REORTH] = (2.0 * ns_iters + 2.0) * 3.0 * 8.0 * rr * rr;
+            }
         }
     }
     return status;
 }
+
+
+}  // extern "C"
+
+namespace {
+
+size_t take_bytes(size_t &o, size_t bytes)
+{
+    const size_t at = o;
+    o = (o + bytes + 255) / 256 * 256;
+    return at;
+}
+
+}  // namespace
+
+extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n, const int *p,
+                                          const long long *off, const long long *voff, const double *G,
+                                          const hsvd_params *prm_in, double *sigma, double *U, double *V,
+                                          double *lambda, int *status_out, int *sweeps_out, hsvd_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    if (!ctx || batch < 0) return HSVD_E_INVAL;
+    if (batch == 0) return HSVD_OK;
+    if (!n || !p || !off || !voff || !G || !sigma) return HSVD_E_INVAL;
+    hsvd_params prm;
+    if (prm_in) prm = *prm_in;
+    else hsvd_default_params(&prm);
+    if (prm.precision != HSVD_FP64) return HSVD_E_INVAL;
+    if (prm.ordering != HSVD_ORD_MODMOD && prm.ordering != HSVD_ORD_ROUNDROBIN) return HSVD_E_INVAL;
+    if (prm.block != 0 && prm.block != block_width()) return HSVD_E_INVAL;
+    const bool want_v = prm.want_v != 0;
+    if (V && !want_v) return HSVD_E_INVAL;
+    for (int k = 0; k < batch; ++k)
+        if (n[k] < 1 || n[k] > 1024 || p[k] < 0 || p[k] > n[k] || off[k] < 0 || voff[k] < 0) return HSVD_E_INVAL;
+    const int max_sweeps = prm.max_sweeps > 0 ? prm.max_sweeps : 100;
+    const int b = block_width();
+    HSVD_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    hsvd_status s = ensure_events(ctx, 4 + 4 * 1024 / b);
+    if (s != HSVD_OK) return s;
+    hipEvent_t *ev = ctx->events.data();
+
+    // group the problems by bordered order r = n rounded up to 2b
+    std::vector<std::vector<int>> groups(1024 / (2 * b) + 1);
+    for (int k = 0; k < batch; ++k) groups[(n[k] + 2 * b - 1) / (2 * b)].push_back(k);
+
+    double kms[HSVD_NKERNELS] = {0};
+    long long klaunch[HSVD_NKERNELS] = {0};
+    double kbytes[HSVD_NKERNELS] = {0}, kflops[HSVD_NKERNELS] = {0};
+    long long tot_rot = 0, tot_skip = 0, tot_act = 0, tot_steps = 0;
+    int max_sw = 0;
+    std::vector<int> all_status(batch, HSVD_OK), all_sweeps(batch, 0);
+    HSVD_TRY(hipEventRecord(ev[0], st));
+    for (size_t gi = 1; gi < groups.size(); ++gi) {
+        const std::vector<int> &ids = groups[gi];
+        if (ids.empty()) continue;
+        const int K = (int)ids.size();
+        const int r = (int)gi * 2 * b, ldg = r, nb = r / b, pairs = nb / 2;
+        const int steps_per_sweep = prm.ordering == HSVD_ORD_MODMOD ? nb : nb - 1;
+        const size_t mat = (size_t)ldg * r, bb = (size_t)4 * b * b;
+        // workspace of the group
+        size_t o = 0;
+        const size_t o_ids = take_bytes(o, sizeof(int) * K), o_n = take_bytes(o, sizeof(int) * K);
+        const size_t o_p = take_bytes(o, sizeof(int) * K), o_done = take_bytes(o, sizeof(int) * K);
+        const size_t o_stat = take_bytes(o, sizeof(int) * K), o_sw = take_bytes(o, sizeof(int) * K);
+        const size_t o_off = take_bytes(o, sizeof(long long) * K), o_voff = take_bytes(o, sizeof(long long) * K);
+        const size_t o_tol = take_bytes(o, sizeof(double) * K), o_tth = take_bytes(o, sizeof(double) * K);
+        const size_t o_cnt = take_bytes(o, sizeof(int));
+        const size_t o_G = take_bytes(o, sizeof(double) * mat * K);
+        const size_t o_V = take_bytes(o, want_v ? sizeof(double) * mat * K : 0);
+        const size_t o_d = take_bytes(o, sizeof(double) * r * K), o_dt = take_bytes(o, sizeof(double) * r * K);
+        const size_t o_rho = take_bytes(o, sizeof(int) * r * K), o_rt = take_bytes(o, sizeof(int) * r * K);
+        const size_t o_C = take_bytes(o, sizeof(int) * pairs * K);
+        const size_t o_nr = take_bytes(o, sizeof(unsigned) * pairs * K);
+        const size_t o_ns = take_bytes(o, sizeof(unsigned) * pairs * K);
+        const size_t o_na = take_bytes(o, sizeof(unsigned) * pairs * K);
+        const size_t o_mt = take_bytes(o, sizeof(double) * pairs * K);
+        const size_t o_ctl = take_bytes(o, sizeof(Ctl) * K);
+        const size_t o_S2 = take_bytes(o, sizeof(int4) * 2 * pairs);
+        const size_t o_P = take_bytes(o, sizeof(double) * pairs * bb * K);
+        const size_t o_W = take_bytes(o, sizeof(double) * pairs * bb * K);
+        const size_t o_act = take_bytes(o, sizeof(int) * pairs * K);
+        s = ensure_ws(ctx, o);
+        if (s != HSVD_OK) return s;
+        char *base = static_cast<char *>(ctx->ws);
+        // per-problem metadata
+        std::vector<int> hn(K), hp(K);
+        std::vector<long long> hoff(K), hvoff(K);
+        std::vector<double> htol(K), htth(K);
+        for (int z = 0; z < K; ++z) {
+            const int k = ids[z];
+            hn[z] = n[k];
+            hp[z] = p[k];
+            hoff[z] = off[k];
+            hvoff[z] = voff[k];
+            htol[z] = prm.tol > 0.0 ? prm.tol : 1e-15 * n[k];
+            htth[z] = prm.t_thresh > 0.0 ? prm.t_thresh : sqrt(htol[z]) / 2.0;
+        }
+        HSVD_TRY(hipMemcpyAsync(base + o_ids, ids.data(), sizeof(int) * K, hipMemcpyHostToDevice, st));
+        HSVD_TRY(hipMemcpyAsync(base + o_n, hn.data(), sizeof(int) * K, hipMemcpyHostToDevice, st));
+        HSVD_TRY(hipMemcpyAsync(base + o_p, hp.data(), sizeof(int) * K, hipMemcpyHostToDevice, st));
+        HSVD_TRY(hipMemcpyAsync(base + o_off, hoff.data(), sizeof(long long) * K, hipMemcpyHostToDevice, st));
+        HSVD_TRY(hipMemcpyAsync(base + o_voff, hvoff.data(), sizeof(long long) * K, hipMemcpyHostToDevice, st));
+        HSVD_TRY(hipMemcpyAsync(base + o_tol, htol.data(), sizeof(double) * K, hipMemcpyHostToDevice, st));
+        HSVD_TRY(hipMemcpyAsync(base + o_tth, htth.data(), sizeof(double) * K, hipMemcpyHostToDevice, st));
+        HSVD_TRY(hipStreamSynchronize(st));
+
+        BatchGroup g;
+        g.nprob = K;
+        g.r = r;
+        g.ldg = ldg;
+        g.pairs = pairs;
+        g.max_sweeps = max_sweeps;
+        g.ids = reinterpret_cast<int *>(base + o_ids);
+        g.n = reinterpret_cast<int *>(base + o_n);
+        g.p = reinterpret_cast<int *>(base + o_p);
+        g.off = reinterpret_cast<long long *>(base + o_off);
+        g.voff = reinterpret_cast<long long *>(base + o_voff);
+        g.tol = reinterpret_cast<double *>(base + o_tol);
+        g.tth = reinterpret_cast<double *>(base + o_tth);
+        g.done = reinterpret_cast<int *>(base + o_done);
+        g.status = reinterpret_cast<int *>(base + o_stat);
+        g.sweeps = reinterpret_cast<int *>(base + o_sw);
+        g.active_count = reinterpret_cast<int *>(base + o_cnt);
+        g.G = reinterpret_cast<double *>(base + o_G);
+        g.V = want_v ? reinterpret_cast<double *>(base + o_V) : nullptr;
+        g.d = reinterpret_cast<double *>(base + o_d);
+        g.dtmp = reinterpret_cast<double *>(base + o_dt);
+        g.rho = reinterpret_cast<int *>(base + o_rho);
+        g.rtmp = reinterpret_cast<int *>(base + o_rt);
+        g.C = reinterpret_cast<int *>(base + o_C);
+        g.nrot = reinterpret_cast<unsigned *>(base + o_nr);
+        g.nskip = reinterpret_cast<unsigned *>(base + o_ns);
+        g.nact = reinterpret_cast<unsigned *>(base + o_na);
+        g.maxt = reinterpret_cast<double *>(base + o_mt);
+        g.ctl = reinterpret_cast<Ctl *>(base + o_ctl);
+        int4 *S2 = reinterpret_cast<int4 *>(base + o_S2);
+
+        HSVD_TRY(launch_batch_setup(st, g, G, want_v));
+        HSVD_TRY(launch_block_stepper_init(st, S2, nb));
+        if (prm.sort) HSVD_TRY(launch_batch_sort(st, g));
+
+        BlockArgs ba;
+        ba.G = g.G;
+        ba.V = g.V;
+        ba.ldg = ldg;
+        ba.r = r;
+        ba.p = 0;
+        ba.nb = nb;
+        ba.rho = g.rho;
+        ba.ordering = prm.ordering;
+        ba.partial = reinterpret_cast<double *>(base + o_P);
+        ba.splits = 1;
+        ba.rows_per_split = ldg;
+        ba.W = reinterpret_cast<double *>(base + o_W);
+        ba.active = reinterpret_cast<int *>(base + o_act);
+        ba.C = g.C;
+        ba.nrot = g.nrot;
+        ba.nskip = g.nskip;
+        ba.nact = g.nact;
+        ba.maxt = g.maxt;
+        ba.ctl = g.ctl;
+        ba.tol = 0.0;
+        ba.tthresh = 0.0;
+        ba.nprob = K;
+        ba.done = g.done;
+        ba.pvec = g.p;
+        ba.tolvec = g.tol;
+        ba.tthvec = g.tth;
+        long long gstep = 0;
+        int gsweeps = 0;
+        for (int sw = 0; sw < max_sweeps; ++sw) {
+            for (int k = 0; k < steps_per_sweep; ++k, ++gstep) {
+                ba.step = k;
+                ba.S_in = S2 + (gstep & 1) * pairs;
+                ba.S_out = S2 + ((gstep + 1) & 1) * pairs;
+                hipEvent_t *e = ev + 4 + 4 * k;
+                HSVD_TRY(hipEventRecord(e[0], st));
+                HSVD_TRY(launch_block_gram<double>(st, ba));
+                HSVD_TRY(hipEventRecord(e[1], st));
+                HSVD_TRY(launch_block_inner<double>(st, ba));
+                HSVD_TRY(hipEventRecord(e[2], st));
+                HSVD_TRY(launch_block_update<double>(st, ba));
+                HSVD_TRY(hipEventRecord(e[3], st));
+            }
+            for (int q = 0; q < 3; ++q) klaunch[HSVD_K_BLOCK_GRAM + q] += steps_per_sweep;
+            tot_steps += steps_per_sweep;
+            HSVD_TRY(launch_batch_colnorm(st, g, false));
+            if (prm.sort) HSVD_TRY(launch_batch_sort(st, g));
+            HSVD_TRY(launch_batch_reduce_decide(st, g));
+            int active = 0;
+            HSVD_TRY(hipMemcpyAsync(&ctx->host_ctl->code, g.active_count, sizeof(int), hipMemcpyDeviceToHost, st));
+            HSVD_TRY(hipStreamSynchronize(st));
+            active = ctx->host_ctl->code;
+            for (int k = 0; k < steps_per_sweep; ++k) {
+                hipEvent_t *e = ev + 4 + 4 * k;
+                for (int q = 0; q < 3; ++q) {
+                    float ms = 0.f;
+                    HSVD_TRY(hipEventElapsedTime(&ms, e[q], e[q + 1]));
+                    kms[HSVD_K_BLOCK_GRAM + q] += ms;
+                }
+            }
+            ++gsweeps;
+            if (active == 0) break;
+        }
+        HSVD_TRY(launch_batch_finalize(st, g, sigma, U, want_v ? V : nullptr, lambda));
+        std::vector<int> hs(K), hsw(K);
+        std::vector<Ctl> hctl(K);
+        HSVD_TRY(hipMemcpyAsync(hs.data(), g.status, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+        HSVD_TRY(hipMemcpyAsync(hsw.data(), g.sweeps, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+        HSVD_TRY(hipMemcpyAsync(hctl.data(), g.ctl, sizeof(Ctl) * K, hipMemcpyDeviceToHost, st));
+        HSVD_TRY(hipStreamSynchronize(st));
+        long long act = 0;
+        for (int z = 0; z < K; ++z) {
+            all_status[ids[z]] = hs[z];
+            all_sweeps[ids[z]] = hsw[z];
+            if (hsw[z] > max_sw) max_sw = hsw[z];
+            tot_rot += (long long)hctl[z].rot;
+            tot_skip += (long long)hctl[z].skip;
+            act += (long long)hctl[z].act;
+        }
+        tot_act += act;
+        // algorithmic work of the group (see hsvd_solve): Gram of every pair
+        // step of every problem still running, update of the active ones
+        long long visits = 0;
+        for (int z = 0; z < K; ++z) visits += (long long)hsw[z] * steps_per_sweep * pairs;
+        const double b2 = 2.0 * b, rows = (double)ldg, vmul = want_v ? 2.0 : 1.0;
+        kbytes[HSVD_K_BLOCK_GRAM] += (double)visits * 8.0 * b2 * rows;
+        kflops[HSVD_K_BLOCK_GRAM] += (double)visits * 2.0 * b2 * b2 * rows;
+        kbytes[HSVD_K_BLOCK_INNER] += (double)visits * 3.0 * 8.0 * b2 * b2;
+        kbytes[HSVD_K_BLOCK_UPDATE] += (double)act * 16.0 * b2 * rows * vmul;
+        kflops[HSVD_K_BLOCK_UPDATE] += (double)act * 2.0 * b2 * b2 * rows * vmul;
+        (void)gsweeps;
+    }
+    HSVD_TRY(hipEventRecord(ev[1], st));
+    HSVD_TRY(hipStreamSynchronize(st));
+    hsvd_status result = HSVD_OK;
+    for (int k = 0; k < batch; ++k) {
+        if (status_out) status_out[k] = all_status[k];
+        if (sweeps_out) sweeps_out[k] = all_sweeps[k];
+        if (result == HSVD_OK && all_status[k] != HSVD_OK) result = (hsvd_status)all_status[k];
+    }
+    if (info) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ev[0], ev[1]);
+        info->status = result;
+        info->sweeps = max_sw;
+        info->block = b;
+        info->rotations = tot_rot;
+        info->skips = tot_skip;
+        info->steps = tot_steps;
+        info->active_pairs = tot_act;
+        info->ms_total = ms;
+        for (int q = 0; q < HSVD_NKERNELS; ++q) {
+            info->kernel_ms[q] = kms[q];
+            info->kernel_launches[q] = klaunch[q];
+            info->kernel_bytes[q] = kbytes[q];
+            info->kernel_flops[q] = kflops[q];
+        }
+    }
+    return result;
+}
+
+extern "C" {
 
 hsvd_status hsvd_pair_params(hsvd_ctx *ctx, long long m, const double *aii, const double *ajj,
                              const double *aij, const int *hyp, double tol, double t_thresh, int *skip,

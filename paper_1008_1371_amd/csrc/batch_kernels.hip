@@ -1,0 +1,264 @@
+// Batched solves: many independent problems of uneven order and signature.
+//
+// The library groups the problems by their bordered order r (a multiple of 2b)
+// and runs the block path over a whole group at once: every launch of the
+// Gram / inner / update kernels covers all (problem, block pair) tasks of a
+// step, so the latency-bound inner solves of thousands of small problems run
+// side by side.  These kernels are the per-problem set-up, the kept diagonal,
+// the sort, the per-problem stop rule (eq. 4.2) and the output extraction;
+// each problem converges, and stops being worked on, on its own.
+#include "internal.h"
+
+namespace hsvd {
+
+// Bordered working copy of problem z (eq. 4.1) and V = I.  grid (r, nprob)
+__global__ __launch_bounds__(256) void batch_setup_kernel(BatchGroup g, const double *__restrict__ Gin,
+                                                          int want_v)
+{
+    const int c = blockIdx.x, z = blockIdx.y;
+    const int n = g.n[z];
+    const size_t mat = (size_t)g.ldg * g.r;
+    double *gc = g.G + z * mat + (size_t)c * g.ldg;
+    double *vc = want_v ? g.V + z * mat + (size_t)c * g.ldg : nullptr;
+    const double *src = Gin + g.off[z] + (size_t)c * n;
+    for (int row = threadIdx.x; row < g.ldg; row += 256) {
+        double v;
+        if (c < n)
+            v = row < n ? src[row] : 0.0;
+        else
+            v = row == c ? 1.0 : 0.0;
+        gc[row] = v;
+        if (vc) vc[row] = row == c ? 1.0 : 0.0;
+    }
+}
+
+// d[z][q] = ||G_z[:, rho_z[q]]||^2.  With init: rho = id, per-problem slot
+// counters cleared, non-finite / zero columns flagged.  grid (r, nprob)
+__global__ __launch_bounds__(256) void batch_colnorm_kernel(BatchGroup g, int init)
+{
+    __shared__ double sh[4];
+    const int q = blockIdx.x, z = blockIdx.y;
+    if (!init && g.done[z]) return;
+    const size_t mat = (size_t)g.ldg * g.r;
+    int *rho = g.rho + (size_t)z * g.r;
+    const int c = init ? q : rho[q];
+    const double *gc = g.G + z * mat + (size_t)c * g.ldg;
+    double s = 0.0;
+    for (int row = threadIdx.x; row < g.ldg; row += 256) {
+        const double x = gc[row];
+        s = fma(x, x, s);
+    }
+    s = block_sum<256>(s, sh);
+    if (threadIdx.x == 0) {
+        g.d[(size_t)z * g.r + q] = s;
+        if (init) {
+            rho[q] = q;
+            Ctl *ctl = g.ctl + z;
+            if (!isfinite(s)) atomicOr(&ctl->inval, 1);
+            else if (!(s > 0.0)) atomicOr(&ctl->rank, 1);
+            if (q < g.pairs) {
+                const size_t k = (size_t)z * g.pairs + q;
+                g.C[k] = 0;
+                g.nrot[k] = 0;
+                g.nskip[k] = 0;
+                g.nact[k] = 0;
+                g.maxt[k] = 0.0;
+            }
+        }
+    }
+}
+
+// Stable diagonal sort of each problem (positions [0, p) by d decreasing,
+// [p, r) increasing), one workgroup per problem (r <= 1024).  grid nprob
+__global__ __launch_bounds__(1024) void batch_sort_kernel(BatchGroup g)
+{
+    __shared__ double key[1024];
+    __shared__ int val[1024];
+    const int z = blockIdx.x;
+    if (g.done[z]) return;
+    const int r = g.r, p = g.p[z];
+    double *d = g.d + (size_t)z * r;
+    int *rho = g.rho + (size_t)z * r;
+    const int q = threadIdx.x;
+    if (q < r) {
+        key[q] = d[q];
+        val[q] = rho[q];
+    }
+    __syncthreads();
+    if (q < r) {
+        const double kq = key[q];
+        const bool pos = q < p;
+        const int lo = pos ? 0 : p, hi = pos ? p : r;
+        int cnt = 0;
+        for (int u = lo; u < hi; ++u) {
+            const double kv = key[u];
+            const bool before = pos ? (kv > kq) : (kv < kq);
+            cnt += (before || (kv == kq && u < q)) ? 1 : 0;
+        }
+        d[lo + cnt] = kq;
+        rho[lo + cnt] = val[q];
+    }
+}
+
+// After the set-up: problems with a non-finite entry or a zero column stop at once.
+__global__ void batch_init_decide_kernel(BatchGroup g)
+{
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= g.nprob) return;
+    const Ctl *ctl = g.ctl + z;
+    g.sweeps[z] = 0;
+    if (ctl->inval) {
+        g.status[z] = HSVD_E_INVAL;
+        g.done[z] = 1;
+    } else if (ctl->rank) {
+        g.status[z] = HSVD_E_RANK;
+        g.done[z] = 1;
+    } else {
+        g.status[z] = HSVD_OK;
+        g.done[z] = 0;
+    }
+}
+
+// End of a sweep: per problem, OR of the slot codes and the stop rule of
+// eq. (4.2); problems still running are counted.  grid nprob, 64 threads
+__global__ __launch_bounds__(64) void batch_reduce_decide_kernel(BatchGroup g)
+{
+    const int z = blockIdx.x;
+    if (g.done[z]) return;
+    int code = 0;
+    unsigned long long rot = 0, skp = 0, act = 0;
+    double mx = 0.0;
+    for (int q = threadIdx.x; q < g.pairs; q += 64) {
+        const size_t k = (size_t)z * g.pairs + q;
+        code |= g.C[k];
+        rot += g.nrot[k];
+        skp += g.nskip[k];
+        act += g.nact[k];
+        mx = fmax(mx, g.maxt[k]);
+        g.C[k] = 0;
+        g.nrot[k] = 0;
+        g.nskip[k] = 0;
+        g.nact[k] = 0;
+        g.maxt[k] = 0.0;
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        code |= __shfl_xor(code, m, 64);
+        rot += __shfl_xor(rot, m, 64);
+        skp += __shfl_xor(skp, m, 64);
+        act += __shfl_xor(act, m, 64);
+        mx = fmax(mx, __shfl_xor(mx, m, 64));
+    }
+    if (threadIdx.x == 0) {
+        Ctl *ctl = g.ctl + z;
+        ctl->code = code;
+        ctl->rot += rot;
+        ctl->skip += skp;
+        ctl->act += act;
+        ctl->maxt = mx;
+        const int sw = g.sweeps[z] + 1;
+        g.sweeps[z] = sw;
+        if (ctl->rank) {
+            g.status[z] = HSVD_E_RANK;
+            g.done[z] = 1;
+        } else if ((code & 2) == 0) {
+            g.status[z] = HSVD_OK;
+            g.done[z] = 1;
+        } else if (sw >= g.max_sweeps) {
+            g.status[z] = HSVD_E_NOCONV;
+            g.done[z] = 1;
+        } else {
+            atomicAdd(g.active_count, 1);
+        }
+    }
+}
+
+// sigma, U = G Sigma^{-1}, lambda, V of problem z into the packed outputs.
+// grid (r, nprob)
+__global__ __launch_bounds__(256) void batch_finalize_kernel(BatchGroup g, double *__restrict__ sigma,
+                                                             double *__restrict__ U, double *__restrict__ V,
+                                                             double *__restrict__ lambda)
+{
+    const int q = blockIdx.x, z = blockIdx.y;
+    const int n = g.n[z], p = g.p[z];
+    const int c = g.rho[(size_t)z * g.r + q];
+    if (c >= n) return;
+    const double dq = g.d[(size_t)z * g.r + q];
+    const double s = sqrt(dq);
+    const long long vo = g.voff[z], mo = g.off[z];
+    if (threadIdx.x == 0) {
+        sigma[vo + c] = s;
+        if (lambda) lambda[vo + c] = q < p ? dq : -dq;
+    }
+    const size_t mat = (size_t)g.ldg * g.r;
+    const double *gc = g.G + z * mat + (size_t)c * g.ldg;
+    if (U)
+        for (int row = threadIdx.x; row < n; row += 256) U[mo + (size_t)c * n + row] = gc[row] / s;
+    if (V && g.V) {
+        const double *vc = g.V + z * mat + (size_t)c * g.ldg;
+        for (int row = threadIdx.x; row < n; row += 256) V[mo + (size_t)c * n + row] = vc[row];
+    }
+}
+
+__global__ void batch_zero_ctl_kernel(Ctl *ctl, int nprob, int *active_count)
+{
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z == 0) *active_count = 0;
+    if (z >= nprob) return;
+    ctl[z].code = 0;
+    ctl[z].rank = 0;
+    ctl[z].inval = 0;
+    ctl[z].pad = 0;
+    ctl[z].rot = 0;
+    ctl[z].skip = 0;
+    ctl[z].act = 0;
+    ctl[z].maxt = 0.0;
+    ctl[z].nsres = 0.0;
+}
+
+__global__ void batch_zero_count_kernel(int *active_count) { *active_count = 0; }
+
+hipError_t launch_batch_setup(hipStream_t st, const BatchGroup &g, const double *G, bool want_v)
+{
+    batch_zero_ctl_kernel<<<(g.nprob + 255) / 256, 256, 0, st>>>(g.ctl, g.nprob, g.active_count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    batch_setup_kernel<<<dim3(g.r, g.nprob), 256, 0, st>>>(g, G, want_v ? 1 : 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    batch_colnorm_kernel<<<dim3(g.r, g.nprob), 256, 0, st>>>(g, 1);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    batch_init_decide_kernel<<<(g.nprob + 255) / 256, 256, 0, st>>>(g);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_colnorm(hipStream_t st, const BatchGroup &g, bool init)
+{
+    batch_colnorm_kernel<<<dim3(g.r, g.nprob), 256, 0, st>>>(g, init ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sort(hipStream_t st, const BatchGroup &g)
+{
+    batch_sort_kernel<<<g.nprob, 1024, 0, st>>>(g);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce_decide(hipStream_t st, const BatchGroup &g)
+{
+    batch_zero_count_kernel<<<1, 1, 0, st>>>(g.active_count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    batch_reduce_decide_kernel<<<g.nprob, 64, 0, st>>>(g);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(hipStream_t st, const BatchGroup &g, double *sigma, double *U, double *V,
+                                 double *lambda)
+{
+    batch_finalize_kernel<<<dim3(g.r, g.nprob), 256, 0, st>>>(g, sigma, U, V, lambda);
+    return hipGetLastError();
+}
+
+}  // namespace hsvd

@@ -1,4 +1,4 @@
-// Block-column one-sided Jacobi HSVD kernels for gfx950 (FP64 MFMA).
+// Block-column one-sided Jacobi HSVD kernels for gfx950 (FP64 or FP32 MFMA).
 //
 // Positions are split into nb = r / b blocks of b consecutive positions; a
 // parallel step pairs blocks (I, J) by the outer ordering (modified modulus
@@ -19,21 +19,81 @@
 // columns once (circle method over 2b indices, 2b - 1 inner steps); in the
 // other outer steps only the b^2 cross pairs (x, b + ((x + u) mod b)),
 // b inner steps.
+//
+// The kernels are templated on the storage type T of G, V, the partial Grams
+// and W: double for the FP64 path, float for the FP32 sweeps of the mixed
+// path (FP32 MFMA with FP32 accumulation).  The inner solve always runs in
+// FP64 on the promoted Gram matrix; W is rounded to T for the update.
 #include "internal.h"
 
 namespace hsvd {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-// v_mfma_f64_16x16x4f64 lane layout (wave64): operand A element (i, k) and
-// operand B element (k, j) sit in lane i + 16k resp. j + 16k; accumulator
-// register v of lane l holds D(l/16 + 4v, l%16).
+// 16x16x4 MFMA per storage type.  Operand A element (i, k) and operand B
+// element (k, j) sit in lane i + 16k resp. j + 16k for both types; the
+// accumulator layouts differ (checked on the device):
+//   v_mfma_f64_16x16x4f64: register v of lane l holds D(l/16 + 4v, l%16)
+//   v_mfma_f32_16x16x4f32: register v of lane l holds D(4(l/16) + v, l%16)
+template <typename T>
+struct MF;
+template <>
+struct MF<double> {
+    typedef d4 acc;
+    static __device__ __forceinline__ acc zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
+    static __device__ __forceinline__ acc mma(double a, double b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct MF<float> {
+    typedef f4 acc;
+    static __device__ __forceinline__ acc zero() { return f4{0.f, 0.f, 0.f, 0.f}; }
+    static __device__ __forceinline__ acc mma(float a, float b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
 
 constexpr int kB = 32;        // block width b
 constexpr int kB2 = 2 * kB;   // columns of a block pair
 constexpr int kLd = kB2 + 1;  // LDS row stride (doubles)
+constexpr int kMaxSplits = 32; // row splits of the Gram (the host keeps splits <= this)
 
-__device__ __forceinline__ int2 outer_pair(const BlockArgs &a, int k)
+// Points the argument block at problem blockIdx.z of a batched group; false
+// when that problem has already converged.
+template <typename T>
+__device__ __forceinline__ bool bind_problem(BlockArgsT<T> &a)
+{
+    if (a.nprob <= 1 && !a.done) return true;
+    const int z = blockIdx.z;
+    if (a.done && a.done[z]) return false;
+    const size_t mat = (size_t)a.ldg * a.r;
+    const int pairs = a.nb / 2;
+    a.G += z * mat;
+    if (a.V) a.V += z * mat;
+    a.rho += (size_t)z * a.r;
+    a.partial += (size_t)z * pairs * a.splits * (kB2 * kB2);
+    a.W += (size_t)z * pairs * (kB2 * kB2);
+    a.active += (size_t)z * pairs;
+    a.C += (size_t)z * pairs;
+    a.nrot += (size_t)z * pairs;
+    a.nskip += (size_t)z * pairs;
+    a.nact += (size_t)z * pairs;
+    a.maxt += (size_t)z * pairs;
+    a.ctl += z;
+    if (a.pvec) a.p = a.pvec[z];
+    if (a.tolvec) a.tol = a.tolvec[z];
+    if (a.tthvec) a.tthresh = a.tthvec[z];
+    return true;
+}
+
+template <typename T>
+__device__ __forceinline__ int2 outer_pair(const BlockArgsT<T> &a, int k)
 {
     if (a.ordering == HSVD_ORD_MODMOD) {
         const int4 s = a.S_in[k];
@@ -50,10 +110,12 @@ __device__ __forceinline__ int local_pos(int x, int I, int J)
 // ---------------------------------------------------------------------------
 // Gram: partial[k][split] = G_P(rows of split)^T G_P(rows of split)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void block_gram_kernel(BlockArgs a)
+template <typename T>
+__global__ __launch_bounds__(256) void block_gram_kernel(BlockArgsT<T> a)
 {
-    __shared__ double T[kB2 * kLd];
+    __shared__ T Tl[kB2 * kLd];
     __shared__ int cols[kB2];
+    if (!bind_problem(a)) return;
     const int k = blockIdx.x, split = blockIdx.y;
     const int2 IJ = outer_pair(a, k);
     if (threadIdx.x < kB2) cols[threadIdx.x] = a.rho[local_pos(threadIdx.x, IJ.x, IJ.y)];
@@ -61,35 +123,35 @@ __global__ __launch_bounds__(256) void block_gram_kernel(BlockArgs a)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row_begin = split * a.rows_per_split;
     const int row_end = min(a.ldg, row_begin + a.rows_per_split);
-    d4 acc[4];
+    typename MF<T>::acc acc[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < 4; ++q) acc[q] = MF<T>::zero();
     for (int row0 = row_begin; row0 < row_end; row0 += 64) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int idx = threadIdx.x + 256 * e;
             const int c = idx >> 6, rr = idx & 63;
-            T[c * kLd + rr] = a.G[(size_t)cols[c] * a.ldg + row0 + rr];
+            Tl[c * kLd + rr] = a.G[(size_t)cols[c] * a.ldg + row0 + rr];
         }
         __syncthreads();
 #pragma unroll 4
         for (int kk = 0; kk < 16; ++kk) {
             const int rr = kk * 4 + (lane >> 4);
-            const double av = T[(wave * 16 + (lane & 15)) * kLd + rr];
+            const T av = Tl[(wave * 16 + (lane & 15)) * kLd + rr];
 #pragma unroll
             for (int yt = 0; yt < 4; ++yt) {
-                const double bv = T[(yt * 16 + (lane & 15)) * kLd + rr];
-                acc[yt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[yt], 0, 0, 0);
+                const T bv = Tl[(yt * 16 + (lane & 15)) * kLd + rr];
+                acc[yt] = MF<T>::mma(av, bv, acc[yt]);
             }
         }
         __syncthreads();
     }
-    double *out = a.partial + ((size_t)k * a.splits + split) * (kB2 * kB2);
+    T *out = a.partial + ((size_t)k * a.splits + split) * (kB2 * kB2);
 #pragma unroll
     for (int yt = 0; yt < 4; ++yt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int x = wave * 16 + (lane >> 4) + 4 * v;
+            const int x = wave * 16 + MF<T>::row(lane, v);
             const int y = yt * 16 + (lane & 15);
             out[x * kB2 + y] = acc[yt][v];
         }
@@ -98,19 +160,30 @@ __global__ __launch_bounds__(256) void block_gram_kernel(BlockArgs a)
 // ---------------------------------------------------------------------------
 // Inner solve of one block pair.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void block_inner_kernel(BlockArgs a)
+template <typename T>
+__global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
 {
     __shared__ double A[kB2 * kLd];
     __shared__ double Wl[kB2 * kLd];
     __shared__ double pt[kB], pc[kB], pht[kB];
     __shared__ int px[kB], py[kB], prot[kB];
-    __shared__ int s_code, s_rot, s_skip;
+    __shared__ int s_code, s_rot, s_skip, s_any;
+    __shared__ double s_maxt[kB];
+    if (!bind_problem(a)) return;
     const int k = blockIdx.x;
     const int2 IJ = outer_pair(a, k);
-    const double *P = a.partial + (size_t)k * a.splits * (kB2 * kB2);
+    const T *P = a.partial + (size_t)k * a.splits * (kB2 * kB2);
+    // Sum of the partial Grams in split order.  All splits of an entry are
+    // loaded before the sum starts, so the loads overlap.
     for (int idx = threadIdx.x; idx < kB2 * kB2; idx += 256) {
-        double s = P[idx];
-        for (int sp = 1; sp < a.splits; ++sp) s += P[(size_t)sp * (kB2 * kB2) + idx];
+        double v[kMaxSplits];
+#pragma unroll
+        for (int sp = 0; sp < kMaxSplits; ++sp)
+            v[sp] = sp < a.splits ? (double)P[(size_t)sp * (kB2 * kB2) + idx] : 0.0;
+        double s = v[0];
+#pragma unroll
+        for (int sp = 1; sp < kMaxSplits; ++sp)
+            if (sp < a.splits) s += v[sp];
         const int x = idx / kB2, y = idx % kB2;
         A[x * kLd + y] = s;
         Wl[x * kLd + y] = x == y ? 1.0 : 0.0;
@@ -119,12 +192,14 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgs a)
         s_code = 0;
         s_rot = 0;
         s_skip = 0;
+        s_any = 0;
     }
     __syncthreads();
 
     const bool first = a.step == 0;
     const int inner_steps = first ? kB2 - 1 : kB;
     int code = 0, nrot = 0, nskip = 0, rank = 0;
+    double maxt = 0.0;
     for (int u = 0; u < inner_steps; ++u) {
         if (threadIdx.x < kB) {
             const int q = threadIdx.x;
@@ -146,6 +221,7 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgs a)
                     rot = 1;
                     ++nrot;
                     code |= rotation_code(t, a.tthresh);
+                    maxt = fmax(maxt, fabs(t));
                     pht[q] = hyp < 0 ? -t : t;
                 }
             }
@@ -155,8 +231,10 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgs a)
             px[q] = x;
             py[q] = y;
             prot[q] = rot;
+            if (rot) s_any = u + 1;
         }
         __syncthreads();
+        if (s_any != u + 1) continue;  // no rotation in this inner step: A and W unchanged
         // A <- R^T A R on the 2x2 blocks (k1 <= k2), mirrored to keep A symmetric.
         for (int blk = threadIdx.x; blk < kB * kB; blk += 256) {
             const int k1 = blk / kB, k2 = blk % kB;
@@ -210,14 +288,18 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgs a)
         if (nrot) atomicAdd(&s_rot, nrot);
         if (nskip) atomicAdd(&s_skip, nskip);
         if (rank) atomicOr(&a.ctl->rank, 1);
+        s_maxt[threadIdx.x] = maxt;
     }
-    double *Wg = a.W + (size_t)k * (kB2 * kB2);
+    T *Wg = a.W + (size_t)k * (kB2 * kB2);
     for (int idx = threadIdx.x; idx < kB2 * kB2; idx += 256) {
         const int x = idx / kB2, y = idx % kB2;
-        Wg[idx] = Wl[x * kLd + y];
+        Wg[idx] = (T)Wl[x * kLd + y];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        double m = a.maxt[k];
+        for (int q = 0; q < kB; ++q) m = fmax(m, s_maxt[q]);
+        a.maxt[k] = m;
         a.C[k] |= s_code;
         a.nrot[k] += (unsigned)s_rot;
         a.nskip[k] += (unsigned)s_skip;
@@ -227,68 +309,235 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Update: [G_P | V_P] <- [G_P | V_P] W, 256 rows per workgroup.
+// Inner solve of one block pair for the cross steps (every outer step but the
+// first of a sweep), register-resident.
+//
+// Slot coordinates: at inner step u slot s pairs local column L_s = s with
+// R_s(u) = b + ((s + u) mod b).  Thread (s1, s2) of 1024 holds the 2x2 block of
+// A_P with rows {L_s1, R_s1(u)} and columns {L_s2, R_s2(u)}, and the entries of W
+// in rows {s1, b + s1} and columns {L_s2, R_s2(u)}.  The diagonal thread (s, s)
+// holds slot s's pivot entries and computes its rotation; every block is then
+// updated in registers (A <- R^T A R, W <- W R).  Since R_s(u + 1) = R_{s+1}(u),
+// moving to the next inner step is a cyclic shift by one slot of the R-halves:
+// along s2 a lane shuffle within the 32-lane half-wave, along s1 an exchange
+// through LDS.  Blocks (s1, s2) and (s2, s1) apply their column and row
+// operations in mirrored order (columns first iff s1 <= s2), so the two stay
+// exact transposes and A stays exactly symmetric.
 // ---------------------------------------------------------------------------
-constexpr int kUpdRows = 256;
-
-__global__ __launch_bounds__(256) void block_update_kernel(BlockArgs a)
+template <typename T>
+__global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a)
 {
-    __shared__ double Wl[kB2 * kLd];
-    __shared__ double X[kB2 * kLd];
+    __shared__ double prm_t[kB], prm_c[kB], prm_h[kB], s_maxt[kB];
+    __shared__ int prm_rot[kB];
+    __shared__ double sh_rl[kB * kB], sh_rr[kB * kB];
+    __shared__ int s_code, s_rot, s_skip, s_rank;
+    if (!bind_problem(a)) return;
+    const int k = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int s1 = tid >> 5, s2 = tid & 31;
+    const int lane = tid & 63;
+    const int2 IJ = outer_pair(a, k);
+    if (tid == 0) {
+        s_code = 0;
+        s_rot = 0;
+        s_skip = 0;
+        s_rank = 0;
+    }
+
+    // A_P from the partial Grams (upper triangle taken for both mirror entries)
+    const T *P = a.partial + (size_t)k * a.splits * (kB2 * kB2);
+    // two entries at a time, all their splits in flight, summed in split order
+    auto gram2 = [&](int x0, int y0, int x1, int y1, double &g0, double &g1) {
+        const int i0 = min(x0, y0) * kB2 + max(x0, y0);
+        const int i1 = min(x1, y1) * kB2 + max(x1, y1);
+        double v0[kMaxSplits / 2], v1[kMaxSplits / 2];
+        g0 = 0.0;
+        g1 = 0.0;
+        for (int base = 0; base < a.splits; base += kMaxSplits / 2) {
+#pragma unroll
+            for (int q = 0; q < kMaxSplits / 2; ++q) {
+                const bool in = base + q < a.splits;
+                v0[q] = in ? (double)P[(size_t)(base + q) * (kB2 * kB2) + i0] : 0.0;
+                v1[q] = in ? (double)P[(size_t)(base + q) * (kB2 * kB2) + i1] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < kMaxSplits / 2; ++q)
+                if (base + q < a.splits) {
+                    g0 = (base + q == 0) ? v0[q] : g0 + v0[q];
+                    g1 = (base + q == 0) ? v1[q] : g1 + v1[q];
+                }
+        }
+    };
+    double LL, LR, RL, RR;
+    gram2(s1, s2, s1, kB + s2, LL, LR);
+    gram2(kB + s1, s2, kB + s1, kB + s2, RL, RR);
+    double W0L = s1 == s2 ? 1.0 : 0.0, W0R = 0.0, W1L = 0.0, W1R = s1 == s2 ? 1.0 : 0.0;
+    const bool cols_first = s1 <= s2;
+    const bool diag = s1 == s2;
+    int code = 0, nrot = 0, nskip = 0, rank = 0;
+    double maxt = 0.0;
+    const int shsrc = (lane & 32) | ((lane + 1) & 31);  // lane holding slot s2 + 1
+    const int rowsrc = ((s1 + 1) & 31) * kB + s2;         // LDS cell of slot s1 + 1
+
+    for (int u = 0; u < kB; ++u) {
+        if (diag) {
+            const int s = s1;
+            // skip test and rotation evaluated side by side (independent
+            // dependency chains), then selected
+            const int pl = IJ.x * kB + s, pr = IJ.y * kB + ((s + u) & 31);
+            const int hyp = ((pl < a.p) == (pr < a.p)) ? -1 : 1;
+            double t, c;
+            const int bad = rotation_params(LL, RR, LR, hyp, t, c);
+            const bool skip = rel_orthogonal(LL, RR, LR, a.tol);
+            double h = 0.0;
+            int rot = 0;
+            if (skip) {
+                ++nskip;
+                t = 0.0;
+                c = 1.0;
+            } else if (bad) {
+                rank = 1;
+                t = 0.0;
+                c = 1.0;
+            } else {
+                rot = 1;
+                ++nrot;
+                code |= rotation_code(t, a.tthresh);
+                maxt = fmax(maxt, fabs(t));
+                h = hyp < 0 ? -t : t;
+            }
+            prm_t[s] = t;
+            prm_c[s] = c;
+            prm_h[s] = h;
+            prm_rot[s] = rot;
+        }
+        __syncthreads();
+        const double t1 = prm_t[s1], c1 = prm_c[s1], h1 = prm_h[s1];
+        const double t2 = prm_t[s2], c2 = prm_c[s2], h2 = prm_h[s2];
+        // A block: rows (L_s1, R_s1) by slot s1, columns (L_s2, R_s2) by slot s2
+        if (cols_first) {
+            const double f00 = fma(h2, LR, LL) * c2, f01 = fma(t2, LL, LR) * c2;
+            const double f10 = fma(h2, RR, RL) * c2, f11 = fma(t2, RL, RR) * c2;
+            LL = fma(h1, f10, f00) * c1;
+            RL = fma(t1, f00, f10) * c1;
+            LR = fma(h1, f11, f01) * c1;
+            RR = fma(t1, f01, f11) * c1;
+        } else {
+            const double g00 = fma(h1, RL, LL) * c1, g10 = fma(t1, LL, RL) * c1;
+            const double g01 = fma(h1, RR, LR) * c1, g11 = fma(t1, LR, RR) * c1;
+            LL = fma(h2, g01, g00) * c2;
+            LR = fma(t2, g00, g01) * c2;
+            RL = fma(h2, g11, g10) * c2;
+            RR = fma(t2, g10, g11) * c2;
+        }
+        if (diag && prm_rot[s1]) {
+            LR = 0.0;
+            RL = 0.0;
+        }
+        // W columns (L_s2, R_s2) by slot s2
+        {
+            const double a0 = fma(h2, W0R, W0L) * c2, b0 = fma(t2, W0L, W0R) * c2;
+            const double a1 = fma(h2, W1R, W1L) * c2, b1 = fma(t2, W1L, W1R) * c2;
+            W0L = a0;
+            W0R = b0;
+            W1L = a1;
+            W1R = b1;
+        }
+        // shift the R halves by one slot: columns through a lane shuffle ...
+        LR = __shfl(LR, shsrc, 64);
+        RR = __shfl(RR, shsrc, 64);
+        W0R = __shfl(W0R, shsrc, 64);
+        W1R = __shfl(W1R, shsrc, 64);
+        // ... rows through LDS
+        sh_rl[tid] = RL;
+        sh_rr[tid] = RR;
+        __syncthreads();
+        RL = sh_rl[rowsrc];
+        RR = sh_rr[rowsrc];
+    }
+    // after b shifts the slots are back in natural order: R_s = b + s
+    T *Wg = a.W + (size_t)k * (kB2 * kB2);
+    Wg[s1 * kB2 + s2] = (T)W0L;
+    Wg[s1 * kB2 + kB + s2] = (T)W0R;
+    Wg[(kB + s1) * kB2 + s2] = (T)W1L;
+    Wg[(kB + s1) * kB2 + kB + s2] = (T)W1R;
+    if (diag) {
+        if (code) atomicOr(&s_code, code);
+        if (nrot) atomicAdd(&s_rot, nrot);
+        if (nskip) atomicAdd(&s_skip, nskip);
+        if (rank) atomicOr(&s_rank, 1);
+        s_maxt[s1] = maxt;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        if (s_rank) atomicOr(&a.ctl->rank, 1);
+        double m = a.maxt[k];
+        for (int q = 0; q < kB; ++q) m = fmax(m, s_maxt[q]);
+        a.maxt[k] = m;
+        a.C[k] |= s_code;
+        a.nrot[k] += (unsigned)s_rot;
+        a.nskip[k] += (unsigned)s_skip;
+        a.nact[k] += s_rot > 0 ? 1u : 0u;
+        a.active[k] = s_rot > 0 ? 1 : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Update: [G_P | V_P] <- [G_P | V_P] W.
+//
+// Computed transposed, (X W)^T = W^T X^T for each 16-row strip X of G_P (or
+// V_P): the MFMA B operand (k = column x, j = row) is then 16 consecutive rows
+// of one column per 16 lanes, read straight from HBM, and the result lanes
+// (i = output column, j = row) store 16 consecutive rows likewise -- no LDS
+// staging of the data.  W sits in LDS for all strips of the workgroup.
+// ---------------------------------------------------------------------------
+constexpr int kUpdRows = 256;  // rows per workgroup (up to 16 strips of 16 rows, spread over 4 waves)
+
+template <typename T>
+__global__ __launch_bounds__(256) void block_update_kernel(BlockArgsT<T> a)
+{
+    __shared__ T Wl[kB2 * kLd];
     __shared__ int cols[kB2];
     const int k = blockIdx.x;
-    const int tiles_g = a.ldg / kUpdRows;
+    const int tiles_g = (a.ldg + kUpdRows - 1) / kUpdRows;
     const int t = blockIdx.y;
-    if (t == 0 && threadIdx.x == 0 && a.ordering == HSVD_ORD_MODMOD)
+    if (t == 0 && blockIdx.z == 0 && threadIdx.x == 0 && a.ordering == HSVD_ORD_MODMOD)
         a.S_out[k] = modmod_next(a.S_in[k], a.nb);
+    if (!bind_problem(a)) return;
     if (!a.active[k]) return;  // no rotation in this pair: W = I
-    double *M = t < tiles_g ? a.G : a.V;
+    T *__restrict__ M = t < tiles_g ? a.G : a.V;
     const int row_base = (t < tiles_g ? t : t - tiles_g) * kUpdRows;
+    const int nstrips = min(kUpdRows, a.ldg - row_base) / 16;
     const int2 IJ = outer_pair(a, k);
     if (threadIdx.x < kB2) cols[threadIdx.x] = a.rho[local_pos(threadIdx.x, IJ.x, IJ.y)];
-    const double *Wg = a.W + (size_t)k * (kB2 * kB2);
+    const T *Wg = a.W + (size_t)k * (kB2 * kB2);
     for (int idx = threadIdx.x; idx < kB2 * kB2; idx += 256) Wl[(idx / kB2) * kLd + idx % kB2] = Wg[idx];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int sub = 0; sub < kUpdRows / 64; ++sub) {
-        const int row0 = row_base + sub * 64;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll 1
+    for (int strip = wave; strip < nstrips; strip += 4) {
+        const int row0 = row_base + strip * 16;
+        T bv[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int idx = threadIdx.x + 256 * e;
-            const int c = idx >> 6, rr = idx & 63;
-            X[c * kLd + rr] = M[(size_t)cols[c] * a.ldg + row0 + rr];
-        }
-        __syncthreads();
-        d4 acc[4];
+        for (int kk = 0; kk < 16; ++kk) bv[kk] = M[(size_t)cols[4 * kk + lk] * a.ldg + row0 + lr];
+        typename MF<T>::acc acc[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int kk = 0; kk < 16; ++kk) {
-            const int xk = kk * 4 + (lane >> 4);
-            const double av = X[xk * kLd + wave * 16 + (lane & 15)];
+        for (int yt = 0; yt < 4; ++yt) acc[yt] = MF<T>::zero();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
 #pragma unroll
             for (int yt = 0; yt < 4; ++yt) {
-                const double bv = Wl[xk * kLd + yt * 16 + (lane & 15)];
-                acc[yt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[yt], 0, 0, 0);
+                // A(i = y, k = x) = W(x, y), x = 4kk + lk, y = 16yt + lr
+                const T aw = Wl[(4 * kk + lk) * kLd + yt * 16 + lr];
+                acc[yt] = MF<T>::mma(aw, bv[kk], acc[yt]);
             }
-        }
-        __syncthreads();
+        // result D(i = y, j = row): lane holds y = 16yt + MF::row(lane, v), row = row0 + lr
 #pragma unroll
         for (int yt = 0; yt < 4; ++yt)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = wave * 16 + (lane >> 4) + 4 * v;
-                const int y = yt * 16 + (lane & 15);
-                X[y * kLd + row] = acc[yt][v];
-            }
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int idx = threadIdx.x + 256 * e;
-            const int c = idx >> 6, rr = idx & 63;
-            M[(size_t)cols[c] * a.ldg + row0 + rr] = X[c * kLd + rr];
-        }
-        __syncthreads();
+            for (int v = 0; v < 4; ++v)
+                M[(size_t)cols[yt * 16 + MF<T>::row(lane, v)] * a.ldg + row0 + lr] = acc[yt][v];
     }
 }
 
@@ -300,16 +549,17 @@ __global__ void block_stepper_init_kernel(int4 *S, int nb)
 }
 
 // d[pos] = ||G[:, rho[pos]]||^2, one workgroup per position.
-__global__ __launch_bounds__(256) void colnorm_pos_kernel(const double *__restrict__ G, int ldg,
+template <typename T>
+__global__ __launch_bounds__(256) void colnorm_pos_kernel(const T *__restrict__ G, int ldg,
                                                           const int *__restrict__ rho,
                                                           double *__restrict__ d)
 {
     __shared__ double sh[4];
     const int q = blockIdx.x;
-    const double *gc = G + (size_t)rho[q] * ldg;
+    const T *gc = G + (size_t)rho[q] * ldg;
     double s = 0.0;
     for (int row = threadIdx.x; row < ldg; row += 256) {
-        const double x = gc[row];
+        const double x = (double)gc[row];
         s = fma(x, x, s);
     }
     s = block_sum<256>(s, sh);
@@ -364,30 +614,46 @@ hipError_t launch_block_stepper_init(hipStream_t st, int4 *S, int nb)
     return hipGetLastError();
 }
 
-hipError_t launch_block_gram(hipStream_t st, const BlockArgs &a)
+template <typename T>
+hipError_t launch_block_gram(hipStream_t st, const BlockArgsT<T> &a)
 {
-    block_gram_kernel<<<dim3(a.nb / 2, a.splits), 256, 0, st>>>(a);
+    block_gram_kernel<T><<<dim3(a.nb / 2, a.splits, a.nprob), 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_block_inner(hipStream_t st, const BlockArgs &a)
+template <typename T>
+hipError_t launch_block_inner(hipStream_t st, const BlockArgsT<T> &a)
 {
-    block_inner_kernel<<<a.nb / 2, 256, 0, st>>>(a);
+    if (a.step == 0)
+        block_inner_kernel<T><<<dim3(a.nb / 2, 1, a.nprob), 256, 0, st>>>(a);
+    else
+        block_inner_cross_kernel<T><<<dim3(a.nb / 2, 1, a.nprob), 1024, 0, st>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_block_update(hipStream_t st, const BlockArgs &a)
+template <typename T>
+hipError_t launch_block_update(hipStream_t st, const BlockArgsT<T> &a)
 {
-    const int tiles = (a.ldg / kUpdRows) * (a.V ? 2 : 1);
-    block_update_kernel<<<dim3(a.nb / 2, tiles), 256, 0, st>>>(a);
+    const int tiles = ((a.ldg + kUpdRows - 1) / kUpdRows) * (a.V ? 2 : 1);
+    block_update_kernel<T><<<dim3(a.nb / 2, tiles, a.nprob), 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_colnorm_pos(hipStream_t st, const double *G, int ldg, const int *rho, double *d, int r)
+template <typename T>
+hipError_t launch_colnorm_pos(hipStream_t st, const T *G, int ldg, const int *rho, double *d, int r)
 {
-    colnorm_pos_kernel<<<r, 256, 0, st>>>(G, ldg, rho, d);
+    colnorm_pos_kernel<T><<<r, 256, 0, st>>>(G, ldg, rho, d);
     return hipGetLastError();
 }
+
+template hipError_t launch_block_gram<double>(hipStream_t, const BlockArgsT<double> &);
+template hipError_t launch_block_gram<float>(hipStream_t, const BlockArgsT<float> &);
+template hipError_t launch_block_inner<double>(hipStream_t, const BlockArgsT<double> &);
+template hipError_t launch_block_inner<float>(hipStream_t, const BlockArgsT<float> &);
+template hipError_t launch_block_update<double>(hipStream_t, const BlockArgsT<double> &);
+template hipError_t launch_block_update<float>(hipStream_t, const BlockArgsT<float> &);
+template hipError_t launch_colnorm_pos<double>(hipStream_t, const double *, int, const int *, double *, int);
+template hipError_t launch_colnorm_pos<float>(hipStream_t, const float *, int, const int *, double *, int);
 
 hipError_t launch_block_trace(hipStream_t st, int ordering, int r, int b, int step, int4 *S, int *out,
                               bool advance)

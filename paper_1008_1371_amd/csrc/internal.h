@@ -14,9 +14,7 @@
 
 namespace hsvd {
 
-constexpr int kMaxOrder = 16384;   // largest bordered order r (sort keeps r/1024 keys per thread)
-constexpr int kSortThreads = 1024;
-constexpr int kSortPerThread = kMaxOrder / kSortThreads;
+constexpr int kMaxOrder = 16384;   // largest bordered order r
 
 // Per-solve control block in device memory; copied to pinned host memory once per sweep.
 struct Ctl {
@@ -27,6 +25,8 @@ struct Ctl {
     unsigned long long rot;    // rotations, cumulative
     unsigned long long skip;   // skipped pair visits, cumulative
     unsigned long long act;    // block pair steps with a rotation, cumulative
+    double maxt;               // largest |t| of the sweep just reduced
+    double nsres;              // Newton-Schulz residual max |J X^T J X - I| (mixed path)
 };
 
 struct Workspace {
@@ -41,23 +41,31 @@ struct Workspace {
     unsigned int *nrot = nullptr;   // r/2: per-slot rotations in the current sweep
     unsigned int *nskip = nullptr;  // r/2: per-slot skips in the current sweep
     unsigned int *nact = nullptr;   // r/2: per-slot steps with at least one rotation (block path)
+    double *maxt = nullptr;         // r/2: per-slot largest |t| of the current sweep
     Ctl *ctl = nullptr;
     // block path
     double *P = nullptr;      // pairs x splits x (2b)^2 partial Gram matrices
     double *W = nullptr;      // pairs x (2b)^2 accumulated inner transformations
     int *active = nullptr;    // pairs: 1 when the pair's W is not the identity
     int4 *S2 = nullptr;       // 2 x pairs: outer stepper state, double-buffered across steps
+    // mixed path
+    float *G32 = nullptr, *V32 = nullptr, *P32 = nullptr, *W32 = nullptr;
+    double *T1 = nullptr, *T2 = nullptr;  // ldg x r FP64 scratch of the J-re-orthogonalisation
 };
 
 struct Layout {
     int n = 0, r = 0, ldg = 0, pairs = 0, splits = 0, b2 = 0;
     size_t bytes = 0;
     size_t off_G, off_V, off_d, off_rho, off_dtmp, off_rtmp, off_S, off_C, off_nrot, off_nskip,
-        off_nact, off_ctl, off_P, off_W, off_active, off_S2;
+        off_nact, off_maxt, off_ctl, off_P, off_W, off_active, off_S2, off_G32, off_V32, off_P32, off_W32,
+        off_T1, off_T2;
+    bool mixed = false;
 };
 
-// pairs/splits/b2 > 0 adds the block path buffers.
-Layout make_layout(int n, int r, int ldg, bool want_v, int pairs = 0, int splits = 0, int b2 = 0);
+// pairs/splits/b2 > 0 adds the block path buffers, mixed the FP32 copies and
+// the FP64 scratch of the mixed path.
+Layout make_layout(int n, int r, int ldg, bool want_v, int pairs = 0, int splits = 0, int b2 = 0,
+                   bool mixed = false);
 Workspace carve(void *base, const Layout &L);
 
 // ---------------------------------------------------------------------------
@@ -75,41 +83,32 @@ Workspace carve(void *base, const Layout &L);
 __device__ __forceinline__ int rotation_params(double aii, double ajj, double aij, int hyp,
                                                double &t, double &c)
 {
+    // Both cases run the same instruction stream (selects instead of branches,
+    // so a wavefront holding both kinds of pair does not serialise); each case
+    // still rounds exactly the operations listed above, in that order: the
+    // trigonometric root is sqrt(1 + zeta^2) * 1, the hyperbolic one
+    // sqrt(|zeta| - 1) * sqrt(|zeta| + 1).
     const double big = 0x1p500;
+    const bool trig = hyp < 0;
     const double two_aij = 2.0 * aij;
-    if (hyp < 0) {
-        const double zeta = (ajj - aii) / two_aij;
-        const double az = fabs(zeta);
-        const double sg = zeta < 0.0 ? -1.0 : 1.0;
-        double tt;
-        if (az > big) {
-            tt = 0.5 / zeta;
-        } else {
-            const double root = sqrt(1.0 + zeta * zeta);
-            tt = sg / (az + root);
-        }
-        t = tt;
-        c = 1.0 / sqrt(1.0 + tt * tt);
-        return 0;
-    }
-    const double zeta = -(aii + ajj) / two_aij;
+    const double num = trig ? (ajj - aii) : -(aii + ajj);
+    const double zeta = num / two_aij;
     const double az = fabs(zeta);
-    if (!(az > 1.0)) {
-        t = 0.0;
-        c = 1.0;
-        return 1;
-    }
     const double sg = zeta < 0.0 ? -1.0 : 1.0;
-    double tt;
-    if (az > big) {
-        tt = 0.5 / zeta;
-    } else {
-        const double root = sqrt(az - 1.0) * sqrt(az + 1.0);
-        tt = sg / (az + root);
+    const double r1 = sqrt(trig ? 1.0 + zeta * zeta : az - 1.0);
+    const double r2 = trig ? 1.0 : sqrt(az + 1.0);
+    const double root = r1 * r2;
+    double tt = az > big ? 0.5 / zeta : sg / (az + root);
+    const double cin = trig ? 1.0 + tt * tt : (1.0 - tt) * (1.0 + tt);
+    double cc = 1.0 / sqrt(cin);
+    const int bad = (!trig && !(az > 1.0)) ? 1 : 0;
+    if (bad) {
+        tt = 0.0;
+        cc = 1.0;
     }
     t = tt;
-    c = 1.0 / sqrt((1.0 - tt) * (1.0 + tt));
-    return 0;
+    c = cc;
+    return bad;
 }
 
 // Relative orthogonality, eq. (2.3), strict: |a_ij| < tol sqrt(a_ii) sqrt(a_jj).
@@ -227,36 +226,53 @@ struct StepArgs {
     int4 *S;
     int *C;
     unsigned int *nrot, *nskip;
+    double *maxt;
     Ctl *ctl;
     int ordering;    // HSVD_ORD_MODMOD / HSVD_ORD_ROUNDROBIN
     int step;        // step index inside the sweep (round-robin)
     double tol, tthresh;
 };
 
-struct BlockArgs {
-    double *G;
-    double *V;               // nullptr: no V accumulation
+template <typename T>
+struct BlockArgsT {
+    T *G;
+    T *V;                    // nullptr: no V accumulation
     int ldg, r, p, nb;
     const int *rho;
     const int4 *S_in;        // outer stepper state of this step
     int4 *S_out;             // state of the next step (written by the update kernel)
     int ordering, step;      // step: outer step index inside the sweep
-    double *partial;
+    T *partial;
     int splits, rows_per_split;
-    double *W;
+    T *W;
     int *active;
     int *C;
     unsigned int *nrot, *nskip, *nact;
+    double *maxt;            // per slot: largest |t| of the sweep
     Ctl *ctl;
     double tol, tthresh;
+    // Batched solves: problem z = blockIdx.z of a group of problems with the
+    // same bordered order r.  Per-problem arrays are laid out back to back
+    // (G and V every ldg * r elements, rho every r, slots every nb / 2, partial
+    // Grams and W per pair); pvec / tolvec / tthvec give each problem's p and
+    // tolerances and done[z] != 0 skips a problem that has converged.
+    int nprob = 1;
+    const int *done = nullptr;
+    const int *pvec = nullptr;
+    const double *tolvec = nullptr, *tthvec = nullptr;
 };
+typedef BlockArgsT<double> BlockArgs;
 
 int block_width();
 hipError_t launch_block_stepper_init(hipStream_t st, int4 *S, int nb);
-hipError_t launch_block_gram(hipStream_t st, const BlockArgs &a);
-hipError_t launch_block_inner(hipStream_t st, const BlockArgs &a);
-hipError_t launch_block_update(hipStream_t st, const BlockArgs &a);
-hipError_t launch_colnorm_pos(hipStream_t st, const double *G, int ldg, const int *rho, double *d, int r);
+template <typename T>
+hipError_t launch_block_gram(hipStream_t st, const BlockArgsT<T> &a);
+template <typename T>
+hipError_t launch_block_inner(hipStream_t st, const BlockArgsT<T> &a);
+template <typename T>
+hipError_t launch_block_update(hipStream_t st, const BlockArgsT<T> &a);
+template <typename T>
+hipError_t launch_colnorm_pos(hipStream_t st, const T *G, int ldg, const int *rho, double *d, int r);
 hipError_t launch_block_trace(hipStream_t st, int ordering, int r, int b, int step, int4 *S, int *out,
                               bool advance);
 
@@ -274,5 +290,35 @@ hipError_t launch_pair_params(hipStream_t st, long long m, const double *aii, co
                               int *skip, double *t, double *c, int *status, int *code);
 hipError_t launch_pivot_trace(hipStream_t st, int ordering, int r, int steps, int *pairs);
 hipError_t launch_zero_ctl(hipStream_t st, Ctl *ctl);
+
+// Batched solves (one group of problems with a common bordered order r).
+struct BatchGroup {
+    int nprob, r, ldg, pairs, max_sweeps;
+    const int *ids;            // group slot -> problem index
+    const int *n, *p;          // per group slot
+    const long long *off, *voff;
+    const double *tol, *tth;
+    int *done, *status, *sweeps;
+    int *active_count;
+    double *G, *V, *d, *dtmp;
+    int *rho, *rtmp;
+    int *C;
+    unsigned int *nrot, *nskip, *nact;
+    double *maxt;
+    Ctl *ctl;
+};
+hipError_t launch_batch_setup(hipStream_t st, const BatchGroup &g, const double *G, bool want_v);
+hipError_t launch_batch_colnorm(hipStream_t st, const BatchGroup &g, bool init);
+hipError_t launch_batch_sort(hipStream_t st, const BatchGroup &g);
+hipError_t launch_batch_reduce_decide(hipStream_t st, const BatchGroup &g);
+hipError_t launch_batch_finalize(hipStream_t st, const BatchGroup &g, double *sigma, double *U, double *V,
+                                 double *lambda);
+
+// mixed path helpers
+hipError_t launch_to_fp32(hipStream_t st, const double *G, float *G32, float *V32, int ldg, int r);
+hipError_t launch_promote(hipStream_t st, const float *X32, double *X, int ldg, int r);
+hipError_t launch_rowsign(hipStream_t st, const double *X, double *Z, int p, int ldg, int r);
+hipError_t launch_ns_form(hipStream_t st, double *B, int p, int ldg, int r, Ctl *ctl);
+hipError_t launch_copy(hipStream_t st, const double *src, double *dst, int ldg, int r);
 
 }  // namespace hsvd

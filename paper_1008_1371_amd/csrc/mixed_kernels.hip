@@ -1,0 +1,110 @@
+// Helpers of the mixed-precision path: FP32 working copies, and the FP64
+// J-re-orthogonalisation of the V accumulated in FP32.
+//
+// After the FP32 sweeps V32 satisfies V^T J V = J only to FP32 accuracy.  The
+// Newton-Schulz iteration for the J-orthogonal factor,
+//   X <- X (3I - Y) / 2,  Y = J X^T J X  (the J-adjoint of X times X),
+// converges quadratically from X = V32 (promoted) while ||I - Y|| < 1; with X
+// J-orthogonal to FP64 accuracy the FP64 refinement sweeps start from
+// G1 = G X, V0 = X, so the final V = X V_refine is J-orthogonal in FP64.
+// The two products per iteration and G X are plain GEMMs (rocBLAS); these
+// kernels form J X, (3I - J B) / 2 and the residual.
+#include "internal.h"
+
+namespace hsvd {
+
+__global__ __launch_bounds__(256) void to_fp32_kernel(const double *__restrict__ G, float *__restrict__ G32,
+                                                      float *__restrict__ V32, int ldg, int r)
+{
+    const int c = blockIdx.x;
+    for (int row = threadIdx.x; row < ldg; row += 256) {
+        G32[(size_t)c * ldg + row] = (float)G[(size_t)c * ldg + row];
+        if (V32) V32[(size_t)c * ldg + row] = row == c ? 1.f : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void promote_kernel(const float *__restrict__ X32, double *__restrict__ X,
+                                                      int ldg, int r)
+{
+    const int c = blockIdx.x;
+    for (int row = threadIdx.x; row < ldg; row += 256) X[(size_t)c * ldg + row] = (double)X32[(size_t)c * ldg + row];
+}
+
+// Z = J X: row `row` scaled by the sign of physical column `row` (+1 iff row < p).
+__global__ __launch_bounds__(256) void rowsign_kernel(const double *__restrict__ X, double *__restrict__ Z,
+                                                      int p, int ldg, int r)
+{
+    const int c = blockIdx.x;
+    for (int row = threadIdx.x; row < ldg; row += 256) {
+        const double x = X[(size_t)c * ldg + row];
+        Z[(size_t)c * ldg + row] = (row < p || row >= r) ? x : -x;
+    }
+}
+
+// B holds X^T J X (r x r).  Y = J B; B <- (3I - Y) / 2; the largest |Y - I|
+// entry is folded into ctl->nsres (non-negative doubles order like their bit
+// patterns, so an integer max is exact and order independent).
+__global__ __launch_bounds__(256) void ns_form_kernel(double *__restrict__ B, int p, int ldg, int r, Ctl *ctl)
+{
+    __shared__ double sh[256];
+    const int c = blockIdx.x;
+    double m = 0.0;
+    for (int row = threadIdx.x; row < r; row += 256) {
+        const double b = B[(size_t)c * ldg + row];
+        const double y = row < p ? b : -b;
+        const double id = row == c ? 1.0 : 0.0;
+        m = fmax(m, fabs(y - id));
+        B[(size_t)c * ldg + row] = (3.0 * id - y) * 0.5;
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        atomicMax(reinterpret_cast<unsigned long long *>(&ctl->nsres),
+                  static_cast<unsigned long long>(__double_as_longlong(sh[0])));
+}
+
+// dst = src on the r x r block, zero in the padding rows (GEMM results leave
+// the rows beyond r unwritten).
+__global__ __launch_bounds__(256) void copy_kernel(const double *__restrict__ src, double *__restrict__ dst,
+                                                   int ldg, int r)
+{
+    const int c = blockIdx.x;
+    for (int row = threadIdx.x; row < ldg; row += 256)
+        dst[(size_t)c * ldg + row] = row < r ? src[(size_t)c * ldg + row] : 0.0;
+}
+
+hipError_t launch_to_fp32(hipStream_t st, const double *G, float *G32, float *V32, int ldg, int r)
+{
+    to_fp32_kernel<<<r, 256, 0, st>>>(G, G32, V32, ldg, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_promote(hipStream_t st, const float *X32, double *X, int ldg, int r)
+{
+    promote_kernel<<<r, 256, 0, st>>>(X32, X, ldg, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowsign(hipStream_t st, const double *X, double *Z, int p, int ldg, int r)
+{
+    rowsign_kernel<<<r, 256, 0, st>>>(X, Z, p, ldg, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_ns_form(hipStream_t st, double *B, int p, int ldg, int r, Ctl *ctl)
+{
+    ns_form_kernel<<<r, 256, 0, st>>>(B, p, ldg, r, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(hipStream_t st, const double *src, double *dst, int ldg, int r)
+{
+    copy_kernel<<<r, 256, 0, st>>>(src, dst, ldg, r);
+    return hipGetLastError();
+}
+
+}  // namespace hsvd

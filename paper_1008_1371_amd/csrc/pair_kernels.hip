@@ -39,7 +39,8 @@ __global__ __launch_bounds__(WG) void precompute_kernel(const double *__restrict
                                                         int4 *__restrict__ S, int *__restrict__ C,
                                                         unsigned int *__restrict__ nrot,
                                                         unsigned int *__restrict__ nskip,
-                                                        unsigned int *__restrict__ nact, Ctl *ctl)
+                                                        unsigned int *__restrict__ nact,
+                                                        double *__restrict__ maxt, Ctl *ctl)
 {
     __shared__ double sh[WG / 64];
     const int c = blockIdx.x;
@@ -61,6 +62,7 @@ __global__ __launch_bounds__(WG) void precompute_kernel(const double *__restrict
             nrot[c] = 0;
             nskip[c] = 0;
             nact[c] = 0;
+            maxt[c] = 0.0;
         }
     }
 }
@@ -105,6 +107,7 @@ __global__ __launch_bounds__(WG) void pair_step_kernel(StepArgs a)
 
     int code = 0;
     bool rotated = false;
+    double tabs_ = 0.0;
     if (!rel_orthogonal(aii, ajj, aij, a.tol)) {
         const int hyp = ((i < a.p) == (j < a.p)) ? -1 : 1;
         double t, c;
@@ -112,6 +115,7 @@ __global__ __launch_bounds__(WG) void pair_step_kernel(StepArgs a)
             if (threadIdx.x == 0) atomicOr(&a.ctl->rank, 1);
         } else {
             rotated = true;
+            tabs_ = t;
             code = rotation_code(t, a.tthresh);
             const double ht = hyp < 0 ? -t : t;
             double nx = 0.0, ny = 0.0;
@@ -164,6 +168,7 @@ __global__ __launch_bounds__(WG) void pair_step_kernel(StepArgs a)
         if (rotated) {
             a.C[k] |= code;
             a.nrot[k] += 1;
+            a.maxt[k] = fmax(a.maxt[k], fabs(tabs_));
         } else {
             a.nskip[k] += 1;
         }
@@ -172,61 +177,59 @@ __global__ __launch_bounds__(WG) void pair_step_kernel(StepArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Sort_Diagonal: stable rank sort of the two sign segments, one workgroup.
+// Sort_Diagonal: stable rank sort of the two sign segments.
 // Rank of position q = number of positions of its segment whose key must
 // precede it (larger d in [0, p), smaller d in [p, r)) plus equal keys at
 // smaller positions.  Keys are staged through LDS tiles.
 // ---------------------------------------------------------------------------
 constexpr int kSortTile = 2048;
+constexpr int kSortWG = 256;
 
-__global__ __launch_bounds__(kSortThreads) void sort_kernel(double *__restrict__ d, int *__restrict__ rho,
+// Ranks of positions [blockIdx.x * 256, +256): every workgroup scans the keys of
+// the whole order through LDS tiles and scatters its positions' (d, rho) to
+// their ranks in (dtmp, rtmp).
+__global__ __launch_bounds__(kSortWG) void sort_rank_kernel(const double *__restrict__ d,
+                                                            const int *__restrict__ rho,
                                                             double *__restrict__ dtmp,
                                                             int *__restrict__ rtmp, int r, int p)
 {
     __shared__ double tile[kSortTile];
-    double key[kSortPerThread];
-    int cnt[kSortPerThread];
-    const int mine = (r + kSortThreads - 1) / kSortThreads;
-#pragma unroll
-    for (int m = 0; m < kSortPerThread; ++m) {
-        const int q = threadIdx.x + m * kSortThreads;
-        key[m] = (m < mine && q < r) ? d[q] : 0.0;
-        cnt[m] = 0;
-    }
-    for (int base = 0; base < r; base += kSortTile) {
-        const int len = min(kSortTile, r - base);
+    const int q = blockIdx.x * kSortWG + threadIdx.x;
+    const bool valid = q < r;
+    const double kq = valid ? d[q] : 0.0;
+    const bool pos = q < p;
+    const int lo = pos ? 0 : p, hi = pos ? p : r;
+    // positions of this workgroup span [b0, b1); only tiles meeting a segment they use are read
+    const int b0 = blockIdx.x * kSortWG, b1 = min(r, b0 + kSortWG);
+    const int need_lo = b0 < p ? 0 : p, need_hi = b1 - 1 < p ? p : r;
+    int cnt = 0;
+    for (int base = need_lo; base < need_hi; base += kSortTile) {
+        const int len = min(kSortTile, need_hi - base);
         __syncthreads();
-        for (int u = threadIdx.x; u < len; u += kSortThreads) tile[u] = d[base + u];
+        for (int u = threadIdx.x; u < len; u += kSortWG) tile[u] = d[base + u];
         __syncthreads();
-#pragma unroll
-        for (int m = 0; m < kSortPerThread; ++m) {
-            if (m >= mine) break;
-            const int q = threadIdx.x + m * kSortThreads;
-            if (q >= r) continue;
-            const bool pos = q < p;
-            const int lo = pos ? 0 : p, hi = pos ? p : r;
+        if (valid) {
             const int u0 = max(lo, base) - base, u1 = min(hi, base + len) - base;
-            const double kq = key[m];
-            int c = 0;
             for (int u = u0; u < u1; ++u) {
                 const double kv = tile[u];
                 const bool before = pos ? (kv > kq) : (kv < kq);
-                c += (before || (kv == kq && base + u < q)) ? 1 : 0;
+                cnt += (before || (kv == kq && base + u < q)) ? 1 : 0;
             }
-            cnt[m] += c;
         }
     }
-#pragma unroll
-    for (int m = 0; m < kSortPerThread; ++m) {
-        if (m >= mine) break;
-        const int q = threadIdx.x + m * kSortThreads;
-        if (q >= r) continue;
-        const int dst = (q < p ? 0 : p) + cnt[m];
-        dtmp[dst] = key[m];
+    if (valid) {
+        const int dst = lo + cnt;
+        dtmp[dst] = kq;
         rtmp[dst] = rho[q];
     }
-    __syncthreads();
-    for (int q = threadIdx.x; q < r; q += kSortThreads) {
+}
+
+__global__ __launch_bounds__(256) void sort_copy_kernel(double *__restrict__ d, int *__restrict__ rho,
+                                                        const double *__restrict__ dtmp,
+                                                        const int *__restrict__ rtmp, int r)
+{
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q < r) {
         d[q] = dtmp[q];
         rho[q] = rtmp[q];
     }
@@ -238,21 +241,26 @@ __global__ __launch_bounds__(1024) void sweep_reduce_kernel(int *__restrict__ C,
                                                             unsigned int *__restrict__ nrot,
                                                             unsigned int *__restrict__ nskip,
                                                             unsigned int *__restrict__ nact,
+                                                            double *__restrict__ maxt,
                                                             int slots, Ctl *ctl)
 {
     __shared__ int scode[16];
     __shared__ unsigned long long srot[16], sskip[16], sact[16];
+    __shared__ double smax[16];
     int code = 0;
     unsigned long long rot = 0, skp = 0, act = 0;
+    double mx = 0.0;
     for (int k = threadIdx.x; k < slots; k += 1024) {
         code |= C[k];
         rot += nrot[k];
         skp += nskip[k];
         act += nact[k];
+        mx = fmax(mx, maxt[k]);
         C[k] = 0;
         nrot[k] = 0;
         nskip[k] = 0;
         nact[k] = 0;
+        maxt[k] = 0.0;
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
@@ -260,6 +268,7 @@ __global__ __launch_bounds__(1024) void sweep_reduce_kernel(int *__restrict__ C,
         rot += __shfl_xor(rot, m, 64);
         skp += __shfl_xor(skp, m, 64);
         act += __shfl_xor(act, m, 64);
+        mx = fmax(mx, __shfl_xor(mx, m, 64));
     }
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
@@ -267,21 +276,25 @@ __global__ __launch_bounds__(1024) void sweep_reduce_kernel(int *__restrict__ C,
         srot[w] = rot;
         sskip[w] = skp;
         sact[w] = act;
+        smax[w] = mx;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int cc = 0;
         unsigned long long rr = 0, ss = 0, aa = 0;
+        double mm = 0.0;
         for (int q = 0; q < 16; ++q) {
             cc |= scode[q];
             rr += srot[q];
             ss += sskip[q];
             aa += sact[q];
+            mm = fmax(mm, smax[q]);
         }
         ctl->code = cc;
         ctl->rot += rr;
         ctl->skip += ss;
         ctl->act += aa;
+        ctl->maxt = mm;
     }
 }
 
@@ -295,6 +308,8 @@ __global__ void zero_ctl_kernel(Ctl *ctl)
         ctl->rot = 0;
         ctl->skip = 0;
         ctl->act = 0;
+        ctl->maxt = 0.0;
+        ctl->nsres = 0.0;
     }
 }
 
@@ -418,7 +433,7 @@ hipError_t launch_setup(hipStream_t st, const double *G, int lda, int n, const W
 hipError_t launch_precompute(hipStream_t st, const Workspace &w, int r, int ldg)
 {
     precompute_kernel<256><<<r, 256, 0, st>>>(w.G, ldg, r, w.d, w.rho, w.S, w.C, w.nrot, w.nskip,
-                                              w.nact, w.ctl);
+                                              w.nact, w.maxt, w.ctl);
     return hipGetLastError();
 }
 
@@ -445,13 +460,17 @@ hipError_t launch_pair_step(hipStream_t st, const StepArgs &a)
 
 hipError_t launch_sort(hipStream_t st, double *d, int *rho, double *dtmp, int *rtmp, int r, int p)
 {
-    sort_kernel<<<1, kSortThreads, 0, st>>>(d, rho, dtmp, rtmp, r, p);
+    const int blocks = (r + kSortWG - 1) / kSortWG;
+    sort_rank_kernel<<<blocks, kSortWG, 0, st>>>(d, rho, dtmp, rtmp, r, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    sort_copy_kernel<<<blocks, 256, 0, st>>>(d, rho, dtmp, rtmp, r);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_reduce(hipStream_t st, const Workspace &w, int slots)
 {
-    sweep_reduce_kernel<<<1, 1024, 0, st>>>(w.C, w.nrot, w.nskip, w.nact, slots, w.ctl);
+    sweep_reduce_kernel<<<1, 1024, 0, st>>>(w.C, w.nrot, w.nskip, w.nact, w.maxt, slots, w.ctl);
     return hipGetLastError();
 }
 

@@ -34,15 +34,19 @@ class hsvd_params(ctypes.Structure):
                 ("t_thresh", ctypes.c_double)]
 
 
-NKERNELS = 4
-K_PAIR_STEP, K_BLOCK_GRAM, K_BLOCK_INNER, K_BLOCK_UPDATE = range(NKERNELS)
-KERNEL_NAMES = ["pair_step_kernel", "block_gram_kernel", "block_inner_kernel",
-                "block_update_kernel"]
+NKERNELS = 8
+(K_PAIR_STEP, K_BLOCK_GRAM, K_BLOCK_INNER, K_BLOCK_UPDATE, K_BLOCK_GRAM32, K_BLOCK_INNER32,
+ K_BLOCK_UPDATE32, K_REORTH) = range(NKERNELS)
+KERNEL_NAMES = ["pair_step_kernel", "block_gram_kernel<double>", "block_inner_kernel<double>",
+                "block_update_kernel<double>", "block_gram_kernel<float>",
+                "block_inner_kernel<float>", "block_update_kernel<float>", "reorth (rocBLAS dgemm)"]
 
 
 class hsvd_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("sweeps", ctypes.c_int), ("code", ctypes.c_int),
                 ("r", ctypes.c_int), ("block", ctypes.c_int), ("ldg", ctypes.c_int),
+                ("sweeps_fp32", ctypes.c_int), ("reorth_iters", ctypes.c_int),
+                ("max_t_last", ctypes.c_double), ("reorth_resid", ctypes.c_double),
                 ("rotations", ctypes.c_longlong), ("skips", ctypes.c_longlong),
                 ("steps", ctypes.c_longlong), ("active_pairs", ctypes.c_longlong),
                 ("ms_total", ctypes.c_double),
@@ -90,9 +94,11 @@ def lib():
     L.hsvd_pivot_trace.argtypes = [vp, ip, ip, ip, vp]
     L.hsvd_sort_diag.argtypes = [vp, ip, ip, vp, vp]
     L.hsvd_block_trace.argtypes = [vp, ip, ip, ip, ip, vp]
+    L.hsvd_solve_batched.argtypes = [vp, ip, vp, vp, vp, vp, vp, ctypes.POINTER(hsvd_params), vp, vp,
+                                     vp, vp, vp, vp, ctypes.POINTER(hsvd_info)]
     L.hsvd_version.restype = ctypes.c_char_p
     for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_pair_params",
-                 "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_block_trace"):
+                 "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_block_trace", "hsvd_solve_batched"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -215,6 +221,54 @@ def hsvd_solve(ctx: Context, G, p: int, params: hsvd_params | None = None, *, wa
     if check and st not in (OK,):
         raise HsvdError(st, "hsvd_solve")
     return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, perm=perm, info=info.as_dict())
+
+
+def hsvd_solve_batched(ctx: Context, ns, ps, G_packed, offs, voffs, params: hsvd_params | None = None,
+                       *, want_u=True, want_v=None, want_lambda=True, out=None, check=True):
+    """Solves many independent problems in one call.
+
+    ns, ps, offs, voffs: host integer sequences (order, +1 signs, element
+    offset of each column-major G_k in G_packed, offset of sigma_k).
+    G_packed: float64 CUDA tensor with all inputs.  Returns a dict with the
+    packed outputs (sigma, U, V, lam: tensors or None), per-problem status and
+    sweeps (NumPy arrays) and the aggregate info."""
+    import numpy as np
+    import torch
+    L = lib()
+    batch = len(ns)
+    prm = params if params is not None else hsvd_default_params()
+    if want_v is None:
+        want_v = bool(prm.want_v)
+    n_a = np.ascontiguousarray(ns, dtype=np.int32)
+    p_a = np.ascontiguousarray(ps, dtype=np.int32)
+    o_a = np.ascontiguousarray(offs, dtype=np.int64)
+    v_a = np.ascontiguousarray(voffs, dtype=np.int64)
+    tot_v = int((v_a + n_a).max()) if batch else 0
+    dev = G_packed.device
+    out = dict(out or {})
+    sigma = out.get("sigma")
+    if sigma is None:
+        sigma = torch.empty(tot_v, dtype=torch.float64, device=dev)
+    U = out.get("U") if want_u else None
+    if want_u and U is None:
+        U = torch.empty_like(G_packed)
+    V = out.get("V") if want_v else None
+    if want_v and V is None:
+        V = torch.empty_like(G_packed)
+    lam = out.get("lambda") if want_lambda else None
+    if want_lambda and lam is None:
+        lam = torch.empty(tot_v, dtype=torch.float64, device=dev)
+    status = np.zeros(batch, dtype=np.int32)
+    sweeps = np.zeros(batch, dtype=np.int32)
+    info = hsvd_info()
+    c = lambda a: ctypes.c_void_p(a.ctypes.data)
+    st = L.hsvd_solve_batched(ctx.handle, batch, c(n_a), c(p_a), c(o_a), c(v_a), _ptr(G_packed),
+                              ctypes.byref(prm), _ptr(sigma), _ptr(U), _ptr(V), _ptr(lam), c(status),
+                              c(sweeps), ctypes.byref(info))
+    if check and st != OK:
+        raise HsvdError(st, "hsvd_solve_batched")
+    return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, statuses=status, sweeps=sweeps,
+                info=info.as_dict())
 
 
 def hsvd_pair_params(ctx: Context, aii, ajj, aij, hyp, tol: float, t_thresh: float):

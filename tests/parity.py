@@ -49,3 +49,15 @@ def twin_spread(G, p, **kw):
     b = dict(b)
     b["U"] = b["U"][::-1, :]
     return compare(b, a, p), a
+
+
+def ordering_spread(G, p, **kw):
+    """Spread between two oracle runs that follow different trajectories: the
+    modified modulus and the round-robin ordering.  The stop rule of eq. (4.2)
+    accepts a sweep whose tangents are all at most T, so any two converged
+    iterates may differ by the residual off-diagonal level over the spectral
+    gaps; a path that takes its own trajectory (the mixed-precision sweeps) is
+    gated against this spread, not against the twin spread."""
+    a = oracle.hsvd(G, p, ordering="modmod", **kw)
+    b = oracle.hsvd(G, p, ordering="roundrobin", **kw)
+    return compare(b, a, p), a

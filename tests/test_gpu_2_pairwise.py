@@ -27,7 +27,7 @@ def test_gauss128(hsvd_ctx, ordering):
     G, p = W.workload("gauss128")
     say("gauss128", ordering)
     ref = oracle.hsvd(G, p, ordering=ordering)
-    res = run_lib(hsvd_ctx, G, p, ordering=0 if ordering == "modmod" else 1)
+    res = run_lib(hsvd_ctx, G, p, algo=1, ordering=0 if ordering == "modmod" else 1)
     _gate(G, p, res, ref)
 
 
@@ -37,16 +37,16 @@ def test_ragged_and_small(hsvd_ctx, n, p):
     G = W.colscaled(n, 2.0, seed=40 + n)
     say("ragged", n, p)
     ref = oracle.hsvd(G, p)
-    res = run_lib(hsvd_ctx, G, p)
+    res = run_lib(hsvd_ctx, G, p, algo=1)
     _gate(G, p, res, ref)
 
 
 def test_unsorted_and_no_v(hsvd_ctx):
     G = W.gaussian(96, seed=5)
     ref = oracle.hsvd(G, 40, sort=False)
-    res = run_lib(hsvd_ctx, G, 40, sort=0)
+    res = run_lib(hsvd_ctx, G, 40, algo=1, sort=0)
     _gate(G, 40, res, ref)
-    res2 = run_lib(hsvd_ctx, G, 40, want_v=0)
+    res2 = run_lib(hsvd_ctx, G, 40, algo=1, want_v=0)
     assert res2["status"] == 0 and res2["V"] is None
     e = compare(res2, ref, 40)
     assert e["sigma_norm"] <= 1e-12 and e["U"] <= 1e-12
@@ -62,15 +62,15 @@ def test_graded1024(hsvd_ctx, p):
     say("graded1024", p)
     spread, ref = twin_spread(G, p, nthreads=0)
     say("   twin spread", spread)
-    res = run_lib(hsvd_ctx, G, p)
+    res = run_lib(hsvd_ctx, G, p, algo=1)
     gate = max(1e-12, 10 * max(spread["U"], spread.get("V", 0.0)))
     _gate(G, p, res, ref, uv_gate=gate)
 
 
 def test_deterministic(hsvd_ctx):
     G = W.gaussian(200, seed=9)
-    a = run_lib(hsvd_ctx, G, 77)
-    b = run_lib(hsvd_ctx, G, 77)
+    a = run_lib(hsvd_ctx, G, 77, algo=1)
+    b = run_lib(hsvd_ctx, G, 77, algo=1)
     for k in ("sigma", "U", "V", "lam", "perm"):
         assert np.array_equal(a[k], b[k]), k
 
@@ -78,7 +78,7 @@ def test_deterministic(hsvd_ctx):
 def test_error_paths(hsvd_ctx):
     from paper_1008_1371_amd import hsvd as H
     G = W.gaussian(16, seed=3)
-    assert run_lib(hsvd_ctx, G, 8, max_sweeps=1)["status"] == H.E_NOCONV
+    assert run_lib(hsvd_ctx, G, 8, algo=1, max_sweeps=1)["status"] == H.E_NOCONV
     Gd = G.copy()
     Gd[:, 12] = Gd[:, 3]
     assert run_lib(hsvd_ctx, Gd, 8, sort=0)["status"] == H.E_RANK
