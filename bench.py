@@ -3,10 +3,14 @@
 
 One "step" is one complete solve (all sweeps until the stop rule of eq. 4.2,
 with Sigma, U, V and lambda extracted) of the named workload, with the input
-already resident in HBM.  Prints one JSON line with the throughput, the
-roofline of the dominant kernel (measured with HIP events on the library's
-stream during the timed solves) and the CPU oracle timed on a bounded sample
-of the same workload.
+already resident in HBM.  The headline compares the mixed-precision path
+(FP32 MFMA block sweeps, FP64 J-re-orthogonalisation, FP64 refinement) with the
+FP64 block path on the same input; `value` is the mixed path's throughput and
+the FP64 path's is reported beside it.  The JSON line also carries the roofline
+of the dominant kernel (HIP events around every launch on the library's
+stream during the timed solves), accuracy invariants of the last solve, the
+CPU oracle timed on a bounded sample of the same workload, and optionally the
+batched solver's throughput on 10,000 small problems.
 """
 from __future__ import annotations
 
@@ -19,6 +23,7 @@ import time
 METRIC = "HSVD time-to-solution n=4096 (mixed vs FP64 GPU) at rel err ≤1e-12; solves/s"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 
 
 def parse():
@@ -27,26 +32,32 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="colscaled4096")
-    ap.add_argument("--path", default="block", choices=["pairwise", "block"])
+    ap.add_argument("--mode", default="both", choices=["both", "fp64", "mixed", "pairwise"],
+                    help="both: mixed is the headline, FP64 block timed beside it")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the bounded oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="also time the batched solver on this many small problems")
     ap.add_argument("--max-sweeps", type=int, default=0,
                     help="stop each solve after this many sweeps (profiling runs only)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB 8 times (scale for the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
 def accuracy(G, p, R):
-    """Invariants of the last solve, in FP64 on the GPU (torch matmuls)."""
+    """Invariants of a solve, in FP64 on the GPU (torch matmuls)."""
     import torch
     n = G.shape[0]
     U, V, s = R["U"], R["V"], R["sigma"]
     j = torch.ones(n, dtype=torch.float64, device=G.device)
     j[p:] = -1.0
     UtU = U.t() @ U
-    off = (UtU - torch.diag(torch.diagonal(UtU))).abs().max().item()
-    out = {"max_offdiag_UtU": off}
+    out = {"max_offdiag_UtU": (UtU - torch.diag(torch.diagonal(UtU))).abs().max().item(),
+           "tol": 1e-15 * n}
     if V is not None:
         VtJV = V.t() @ (V * j[:, None])
         vn = torch.linalg.matrix_norm(V, ord=2).item() ** 2
@@ -71,12 +82,12 @@ def cpu_baseline(G_np, p, total_steps, block, target_s):
     est_solve = dt / max(1, R["steps"]) * total_steps
     mode = f"block ordering, b={block}" if block else "pairwise modified modulus"
     return {"value": 1.0 / est_solve, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle ({mode}) on the same input for the first {R['steps']} of the "
-                       f"{total_steps} outer steps the GPU solve took ({dt:.1f} s); solve time "
+            "sample": (f"oracle ({mode}, FP64) on the same input for the first {R['steps']} of the "
+                       f"{total_steps} outer steps the FP64 GPU solve took ({dt:.1f} s); solve time "
                        f"extrapolated linearly in steps: {est_solve:.0f} s")}
 
 
-def roofline(infos, names):
+def roofline(infos, names, peaks):
     """Roofline of the kernel class with the most measured time."""
     nk = len(names)
     ms = [sum(i["kernel_ms"][q] for i in infos) for q in range(nk)]
@@ -86,10 +97,10 @@ def roofline(infos, names):
     flops = sum(i["kernel_flops"][q] for i in infos)
     avg_s = ms[q] * 1e-3 / launches
     bpl, fpl = byts / launches, flops / launches
-    if flops > 0 and flops / byts * HBM_PEAK_GBS * 1e9 > FP64_PEAK_TFLOPS * 1e12:
+    peak_tf = peaks[q]
+    if flops > 0 and flops / byts * HBM_PEAK_GBS * 1e9 > peak_tf * 1e12:
         ach = fpl / avg_s / 1e12
-        r = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-             "frac": ach / FP64_PEAK_TFLOPS}
+        r = {"bound": "mfma", "achieved": ach, "peak": peak_tf, "unit": "TFLOP/s", "frac": ach / peak_tf}
     else:
         ach = bpl / avg_s / 1e9
         r = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -101,10 +112,48 @@ def roofline(infos, names):
     for k in range(nk):
         L = sum(i["kernel_launches"][k] for i in infos)
         if L:
+            kb = sum(i["kernel_bytes"][k] for i in infos)
+            kf = sum(i["kernel_flops"][k] for i in infos)
             other[names[k]] = {"avg_launch_us": ms[k] * 1e3 / L, "launches_per_solve": L / len(infos),
-                               "ms_per_solve": ms[k] / len(infos)}
+                               "ms_per_solve": ms[k] / len(infos),
+                               "GB/s": kb / (ms[k] * 1e-3) / 1e9 if ms[k] else None,
+                               "TFLOP/s": kf / (ms[k] * 1e-3) / 1e12 if ms[k] and kf else None}
     r["kernels"] = other
     return r
+
+
+def timed(H, ctx, G, p, prm, out, steps, warmup, check):
+    import torch
+    for _ in range(warmup):
+        H.hsvd_solve(ctx, G, p, prm, out=out, check=check)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        R = H.hsvd_solve(ctx, G, p, prm, out=out, check=check)
+        infos.append(R["info"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return 1000.0 * wall / steps, infos, R
+
+
+def batched_line(H, W, ctx, count):
+    import numpy as np
+    import torch
+    ns, ps, Gs = W.batch(count)
+    flat, offs = W.pack_batch(Gs)
+    voffs = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
+    Gd = torch.from_numpy(flat).cuda()
+    prm = H.hsvd_default_params()
+    H.hsvd_solve_batched(ctx, ns, ps, Gd, offs, voffs, prm)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R = H.hsvd_solve_batched(ctx, ns, ps, Gd, offs, voffs, prm)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"problems": count, "n_range": [int(ns.min()), int(ns.max())], "seconds": dt,
+            "solves_per_s": count / dt, "max_sweeps": R["info"]["sweeps"],
+            "all_converged": bool((R["statuses"] == 0).all())}
 
 
 def main():
@@ -119,17 +168,22 @@ def main():
     from paper_1008_1371_amd import hsvd as H
     from paper_1008_1371_amd import workloads as W
 
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(8):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 8}), flush=True)
+        return
+
     H.lib()  # fails loudly if the HIP library is missing
     G_np, p = W.workload(args.workload)
     n = G_np.shape[0]
     dev = torch.device("cuda:0")
     G = torch.from_numpy(np.asfortranarray(G_np)).to(dev)
     ctx = H.Context(0)
-    prm = H.hsvd_default_params(algo=H.PAIRWISE if args.path == "pairwise" else H.BLOCK)
-    check = True
-    if args.max_sweeps > 0:
-        prm.max_sweeps = args.max_sweeps
-        check = False
     out = dict(
         sigma=torch.empty(n, dtype=torch.float64, device=dev),
         U=torch.empty((n, n), dtype=torch.float64, device=dev).t(),
@@ -137,42 +191,58 @@ def main():
         **{"lambda": torch.empty(n, dtype=torch.float64, device=dev)},
         perm=torch.empty(n, dtype=torch.int32, device=dev),
     )
-    for _ in range(args.warmup):
-        H.hsvd_solve(ctx, G, p, prm, out=out, check=check)
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        R = H.hsvd_solve(ctx, G, p, prm, out=out, check=check)
-        infos.append(R["info"])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = 1000.0 * wall / args.steps
+    check = args.max_sweeps <= 0
+    peaks = [FP64_PEAK_TFLOPS] * 4 + [FP32_PEAK_TFLOPS] * 3 + [FP64_PEAK_TFLOPS]
 
+    def params(mode):
+        prm = H.hsvd_default_params(algo=H.PAIRWISE if mode == "pairwise" else H.BLOCK,
+                                    precision=H.MIXED if mode == "mixed" else H.FP64)
+        if args.max_sweeps > 0:
+            prm.max_sweeps = args.max_sweeps
+        return prm
+
+    runs = {}
+    modes = ["fp64", "mixed"] if args.mode == "both" else [args.mode]
+    for mode in modes:
+        ms, infos, R = timed(H, ctx, G, p, params(mode), out, args.steps, args.warmup, check)
+        acc = None if args.no_accuracy else accuracy(G, p, R)
+        runs[mode] = (ms, infos, acc)
+    head = "mixed" if "mixed" in runs else modes[0]
+    ms, infos, acc = runs[head]
     last = infos[-1]
     line = {
         "metric": METRIC,
-        "value": 1000.0 / ms_per_step,
+        "value": 1000.0 / ms,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if head == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "p": p,
-                   "path": f"{args.path}-fp64", "block": last["block"], "ordering": "modmod",
-                   "sort": 1, "want_v": 1, "tol": 1e-15 * n, "sweeps": last["sweeps"],
-                   "rotations": last["rotations"], "steps_per_solve": last["steps"]},
-        "roofline": roofline(infos, H.KERNEL_NAMES),
+        "config": {"workload": args.workload, "n": n, "p": p, "path": f"{head}",
+                   "block": last["block"], "ordering": "modmod", "sort": 1, "want_v": 1,
+                   "tol": 1e-15 * n, "sweeps_fp32": last["sweeps_fp32"], "sweeps_fp64": last["sweeps"],
+                   "reorth_iters": last["reorth_iters"], "rotations": last["rotations"],
+                   "steps_per_solve": last["steps"]},
+        "roofline": roofline(infos, H.KERNEL_NAMES, peaks),
     }
-    if not args.no_accuracy:
-        line["accuracy"] = accuracy(G, p, R)
+    if acc is not None:
+        line["accuracy"] = acc
+    for mode, (m_ms, m_infos, m_acc) in runs.items():
+        if mode == head:
+            continue
+        line[mode] = {"value": 1000.0 / m_ms, "ms_per_step": m_ms, "sweeps": m_infos[-1]["sweeps"],
+                      "roofline": roofline(m_infos, H.KERNEL_NAMES, peaks), "accuracy": m_acc}
+        line["speedup_vs_" + mode] = m_ms / ms
+    if args.batched > 0:
+        line["batched"] = batched_line(H, W, ctx, args.batched)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(G_np, p, last["steps"], last["block"],
+        ref_infos = runs["fp64"][1] if "fp64" in runs else infos
+        line["cpu_baseline"] = cpu_baseline(G_np, p, ref_infos[-1]["steps"], ref_infos[-1]["block"],
                                             args.cpu_seconds)
     print(json.dumps(line), flush=True)
     ctx.close()

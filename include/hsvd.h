@@ -159,6 +159,15 @@ hsvd_status hsvd_pair_params(hsvd_ctx *ctx, long long m, const double *aii, cons
                              const double *aij, const int *hyp, double tol, double t_thresh,
                              int *skip, double *t, double *c, int *status, int *code);
 
+/* As hsvd_pair_params, with the rotation routine of the block path's inner
+ * solves (the same rotation in a shorter dependency chain: one square root and
+ * Newton-refined hardware reciprocal and reciprocal square root; within a few
+ * ulps of hsvd_pair_params; for a_ii = a_jj trigonometric pairs it takes
+ * t = sgn(a_ij)).  Same arguments, errors and synchronisation. */
+hsvd_status hsvd_block_pair_params(hsvd_ctx *ctx, long long m, const double *aii, const double *ajj,
+                                   const double *aij, const int *hyp, double tol, double t_thresh,
+                                   int *skip, double *t, double *c, int *status, int *code);
+
 /* Pivot pairs produced by the device stepper (Algs. 4.3-4.4, or round-robin)
  * for `steps` consecutive steps starting at the first step of sweep 0.
  *   r          even order (2 <= r).

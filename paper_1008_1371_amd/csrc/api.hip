@@ -868,18 +868,32 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
 
 extern "C" {
 
-hsvd_status hsvd_pair_params(hsvd_ctx *ctx, long long m, const double *aii, const double *ajj,
-                             const double *aij, const int *hyp, double tol, double t_thresh, int *skip,
-                             double *t, double *c, int *status, int *code)
+static hsvd_status pair_params_common(hsvd_ctx *ctx, long long m, const double *aii, const double *ajj,
+                                      const double *aij, const int *hyp, double tol, double t_thresh, int *skip,
+                                      double *t, double *c, int *status, int *code, bool fast)
 {
     if (!ctx || m < 0) return HSVD_E_INVAL;
     if (m > 0 && (!aii || !ajj || !aij || !hyp || !skip || !t || !c || !status || !code))
         return HSVD_E_INVAL;
     HSVD_TRY(hipSetDevice(ctx->device));
     HSVD_TRY(launch_pair_params(ctx->stream, m, aii, ajj, aij, hyp, tol, t_thresh, skip, t, c, status,
-                                code));
+                                code, fast));
     HSVD_TRY(hipStreamSynchronize(ctx->stream));
     return HSVD_OK;
+}
+
+hsvd_status hsvd_pair_params(hsvd_ctx *ctx, long long m, const double *aii, const double *ajj,
+                             const double *aij, const int *hyp, double tol, double t_thresh, int *skip,
+                             double *t, double *c, int *status, int *code)
+{
+    return pair_params_common(ctx, m, aii, ajj, aij, hyp, tol, t_thresh, skip, t, c, status, code, false);
+}
+
+hsvd_status hsvd_block_pair_params(hsvd_ctx *ctx, long long m, const double *aii, const double *ajj,
+                                   const double *aij, const int *hyp, double tol, double t_thresh, int *skip,
+                                   double *t, double *c, int *status, int *code)
+{
+    return pair_params_common(ctx, m, aii, ajj, aij, hyp, tol, t_thresh, skip, t, c, status, code, true);
 }
 
 hsvd_status hsvd_pivot_trace(hsvd_ctx *ctx, int ordering, int r, int steps, int *pairs)

@@ -10,9 +10,9 @@
 //                        row ranges; partial Grams summed in a fixed order.
 //   block_inner_kernel   one workgroup per pair: A_P and the accumulated
 //                        transformation W in LDS; rotations of the pointwise
-//                        method (eqs. 2.2-2.5, the same parameter routine as the
-//                        pairwise path) applied two-sided to A_P and to the
-//                        columns of W, in a parallel inner ordering.
+//                        method (eqs. 2.2-2.5, in the short-chain form of
+//                        rotation_params_fast) applied two-sided to A_P and to
+//                        the columns of W, in a parallel inner ordering.
 //   block_update_kernel  [G_P | V_P] <- [G_P | V_P] W on MFMA, row tiles.
 //
 // Inner ordering: in the first outer step of a sweep every pair of the 2b
@@ -110,10 +110,16 @@ __device__ __forceinline__ int local_pos(int x, int I, int J)
 // ---------------------------------------------------------------------------
 // Gram: partial[k][split] = G_P(rows of split)^T G_P(rows of split)
 // ---------------------------------------------------------------------------
+// The Gram matrix is symmetric: only the 10 upper-triangular 16 x 16 tiles
+// (xt <= yt) of the 4 x 4 tiling are formed, 3, 3, 2 and 2 per wave.  Readers
+// take entry (min(x, y), max(x, y)).
+__constant__ int kGramTileX[4][3] = {{0, 0, 0}, {0, 1, 1}, {1, 2, 0}, {2, 3, 0}};
+__constant__ int kGramTileY[4][3] = {{0, 1, 2}, {3, 1, 2}, {3, 2, 0}, {3, 3, 0}};
+
 template <typename T>
 __global__ __launch_bounds__(256) void block_gram_kernel(BlockArgsT<T> a)
 {
-    __shared__ T Tl[kB2 * kLd];
+    __shared__ T Tl[2][kB2 * kLd];
     __shared__ int cols[kB2];
     if (!bind_problem(a)) return;
     const int k = blockIdx.x, split = blockIdx.y;
@@ -121,40 +127,77 @@ __global__ __launch_bounds__(256) void block_gram_kernel(BlockArgsT<T> a)
     if (threadIdx.x < kB2) cols[threadIdx.x] = a.rho[local_pos(threadIdx.x, IJ.x, IJ.y)];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ntiles = wave < 2 ? 3 : 2;
+    int tx[3], ty[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        tx[q] = kGramTileX[wave][q];
+        ty[q] = kGramTileY[wave][q];
+    }
     const int row_begin = split * a.rows_per_split;
     const int row_end = min(a.ldg, row_begin + a.rows_per_split);
-    typename MF<T>::acc acc[4];
+    const int nchunks = (row_end - row_begin) / 64;
+    typename MF<T>::acc acc[3];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = MF<T>::zero();
-    for (int row0 = row_begin; row0 < row_end; row0 += 64) {
+    for (int q = 0; q < 3; ++q) acc[q] = MF<T>::zero();
+    // thread's 16 elements of a 64-row chunk: column idx >> 6, row idx & 63
+    const T *src[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int idx = threadIdx.x + 256 * e;
+        src[e] = a.G + (size_t)cols[idx >> 6] * a.ldg + (idx & 63);
+    }
+    T pre[16];
+    if (nchunks > 0) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) pre[e] = src[e][row_begin];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int idx = threadIdx.x + 256 * e;
-            const int c = idx >> 6, rr = idx & 63;
-            Tl[c * kLd + rr] = a.G[(size_t)cols[c] * a.ldg + row0 + rr];
+            Tl[0][(idx >> 6) * kLd + (idx & 63)] = pre[e];
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunks) {
+            const int row1 = row_begin + (ch + 1) * 64;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) pre[e] = src[e][row1];
+        }
 #pragma unroll 4
         for (int kk = 0; kk < 16; ++kk) {
             const int rr = kk * 4 + (lane >> 4);
-            const T av = Tl[(wave * 16 + (lane & 15)) * kLd + rr];
 #pragma unroll
-            for (int yt = 0; yt < 4; ++yt) {
-                const T bv = Tl[(yt * 16 + (lane & 15)) * kLd + rr];
-                acc[yt] = MF<T>::mma(av, bv, acc[yt]);
+            for (int q = 0; q < 3; ++q) {
+                if (q < ntiles) {
+                    const T av = Tl[buf][(tx[q] * 16 + (lane & 15)) * kLd + rr];
+                    const T bv = Tl[buf][(ty[q] * 16 + (lane & 15)) * kLd + rr];
+                    acc[q] = MF<T>::mma(av, bv, acc[q]);
+                }
+            }
+        }
+        if (ch + 1 < nchunks) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int idx = threadIdx.x + 256 * e;
+                Tl[buf ^ 1][(idx >> 6) * kLd + (idx & 63)] = pre[e];
             }
         }
         __syncthreads();
     }
     T *out = a.partial + ((size_t)k * a.splits + split) * (kB2 * kB2);
 #pragma unroll
-    for (int yt = 0; yt < 4; ++yt)
+    for (int q = 0; q < 3; ++q) {
+        if (q < ntiles) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int x = wave * 16 + MF<T>::row(lane, v);
-            const int y = yt * 16 + (lane & 15);
-            out[x * kB2 + y] = acc[yt][v];
+            for (int v = 0; v < 4; ++v) {
+                const int x = tx[q] * 16 + MF<T>::row(lane, v);
+                const int y = ty[q] * 16 + (lane & 15);
+                out[x * kB2 + y] = acc[q][v];
+            }
         }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -176,15 +219,16 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
     // Sum of the partial Grams in split order.  All splits of an entry are
     // loaded before the sum starts, so the loads overlap.
     for (int idx = threadIdx.x; idx < kB2 * kB2; idx += 256) {
+        const int x = idx / kB2, y = idx % kB2;
+        const int iu = min(x, y) * kB2 + max(x, y);  // the Gram kernel forms the upper triangle
         double v[kMaxSplits];
 #pragma unroll
         for (int sp = 0; sp < kMaxSplits; ++sp)
-            v[sp] = sp < a.splits ? (double)P[(size_t)sp * (kB2 * kB2) + idx] : 0.0;
+            v[sp] = sp < a.splits ? (double)P[(size_t)sp * (kB2 * kB2) + iu] : 0.0;
         double s = v[0];
 #pragma unroll
         for (int sp = 1; sp < kMaxSplits; ++sp)
             if (sp < a.splits) s += v[sp];
-        const int x = idx / kB2, y = idx % kB2;
         A[x * kLd + y] = s;
         Wl[x * kLd + y] = x == y ? 1.0 : 0.0;
     }
@@ -213,7 +257,7 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
             } else {
                 const int px_ = local_pos(x, IJ.x, IJ.y), py_ = local_pos(y, IJ.x, IJ.y);
                 const int hyp = ((px_ < a.p) == (py_ < a.p)) ? -1 : 1;
-                if (rotation_params(axx, ayy, axy, hyp, t, c)) {
+                if (rotation_params_fast(axx, ayy, axy, hyp, t, c)) {
                     rank = 1;
                     t = 0.0;
                     c = 1.0;
@@ -387,7 +431,7 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
             const int pl = IJ.x * kB + s, pr = IJ.y * kB + ((s + u) & 31);
             const int hyp = ((pl < a.p) == (pr < a.p)) ? -1 : 1;
             double t, c;
-            const int bad = rotation_params(LL, RR, LR, hyp, t, c);
+            const int bad = rotation_params_fast(LL, RR, LR, hyp, t, c);
             const bool skip = rel_orthogonal(LL, RR, LR, a.tol);
             double h = 0.0;
             int rot = 0;

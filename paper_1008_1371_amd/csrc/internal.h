@@ -111,6 +111,69 @@ __device__ __forceinline__ int rotation_params(double aii, double ajj, double ai
     return bad;
 }
 
+// Reciprocal and reciprocal square root from the hardware estimates refined by
+// two Newton steps each (the estimate's relative error e becomes ~e^4, far below
+// one ulp); results within about one ulp, not correctly rounded.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+__device__ __forceinline__ double rsq_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double e = fma(-(h * y), y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-(h * y), y, 0.5);
+    return fma(y, e, y);
+}
+
+// The same rotation as rotation_params with a shorter dependency chain, for
+// the latency-bound inner solves of the block path.  With d = a_jj - a_ii,
+// w = 2 a_ij and S = a_ii + a_jj the smaller-magnitude roots are
+//   trig: t = sgn(d) w / (|d| + sqrt(d^2 + w^2)),          c = (1 + t^2)^(-1/2)
+//   hyp:  t = -w / (S + sqrt((S - |w|)(S + |w|))),          c = ((1 - t)(1 + t))^(-1/2)
+// (one square root, one reciprocal and one reciprocal square root instead of
+// three divisions and two or three square roots), rank failure iff S <= |w|.
+// Results agree with rotation_params to within a few ulps; for d = 0 the trig
+// case takes t = sgn(a_ij) (both signs annihilate a_ij).  Entries outside
+// [2^-480, 2^480], where the squares could leave the exponent range, use
+// rotation_params.
+__device__ __forceinline__ int rotation_params_fast(double aii, double ajj, double aij, int hyp, double &t,
+                                                    double &c)
+{
+    const double lo = 0x1p-480, hi = 0x1p480;
+    if (!(aii >= lo && aii <= hi && ajj >= lo && ajj <= hi)) return rotation_params(aii, ajj, aij, hyp, t, c);
+    const double w = 2.0 * aij;
+    if (hyp < 0) {
+        const double d = ajj - aii;
+        const double r2 = fma(d, d, w * w);
+        const double s = r2 * rsq_nr(r2);
+        const double tt = (d < 0.0 ? -w : w) * rcp_nr(fabs(d) + s);
+        t = tt;
+        c = rsq_nr(fma(tt, tt, 1.0));
+        return 0;
+    }
+    const double S = aii + ajj, aw = fabs(w);
+    const double m = S - aw;
+    if (!(m > 0.0)) {
+        t = 0.0;
+        c = 1.0;
+        return 1;
+    }
+    const double q = m * (S + aw);
+    const double s = q * rsq_nr(q);
+    const double tt = -w * rcp_nr(S + s);
+    t = tt;
+    c = rsq_nr((1.0 - tt) * (1.0 + tt));
+    return 0;
+}
+
 // Relative orthogonality, eq. (2.3), strict: |a_ij| < tol sqrt(a_ii) sqrt(a_jj).
 __device__ __forceinline__ bool rel_orthogonal(double aii, double ajj, double aij, double tol)
 {
@@ -287,7 +350,7 @@ hipError_t launch_finalize(hipStream_t st, const Workspace &w, int n, int r, int
                            int *perm);
 hipError_t launch_pair_params(hipStream_t st, long long m, const double *aii, const double *ajj,
                               const double *aij, const int *hyp, double tol, double tthresh,
-                              int *skip, double *t, double *c, int *status, int *code);
+                              int *skip, double *t, double *c, int *status, int *code, bool fast);
 hipError_t launch_pivot_trace(hipStream_t st, int ordering, int r, int steps, int *pairs);
 hipError_t launch_zero_ctl(hipStream_t st, Ctl *ctl);
 

@@ -378,6 +378,7 @@ __global__ __launch_bounds__(1024) void perm_kernel(const int *__restrict__ rho,
 // ---------------------------------------------------------------------------
 // Diagnostics
 // ---------------------------------------------------------------------------
+template <bool kFast>
 __global__ void pair_params_kernel(long long m, const double *__restrict__ aii,
                                    const double *__restrict__ ajj, const double *__restrict__ aij,
                                    const int *__restrict__ hyp, double tol, double tthresh,
@@ -391,7 +392,8 @@ __global__ void pair_params_kernel(long long m, const double *__restrict__ aii,
     int sk = rel_orthogonal(aii[k], ajj[k], aij[k], tol) ? 1 : 0;
     int stt = 0, cd = 0;
     if (!sk) {
-        stt = rotation_params(aii[k], ajj[k], aij[k], hyp[k], tt, cc);
+        stt = kFast ? rotation_params_fast(aii[k], ajj[k], aij[k], hyp[k], tt, cc)
+                    : rotation_params(aii[k], ajj[k], aij[k], hyp[k], tt, cc);
         if (!stt) cd = rotation_code(tt, tthresh);
     }
     skip[k] = sk;
@@ -496,12 +498,16 @@ hipError_t launch_finalize(hipStream_t st, const Workspace &w, int n, int r, int
 
 hipError_t launch_pair_params(hipStream_t st, long long m, const double *aii, const double *ajj,
                               const double *aij, const int *hyp, double tol, double tthresh,
-                              int *skip, double *t, double *c, int *status, int *code)
+                              int *skip, double *t, double *c, int *status, int *code, bool fast)
 {
     if (m == 0) return hipSuccess;
     const long long blocks = (m + 255) / 256;
-    pair_params_kernel<<<(unsigned)blocks, 256, 0, st>>>(m, aii, ajj, aij, hyp, tol, tthresh, skip, t,
-                                                         c, status, code);
+    if (fast)
+        pair_params_kernel<true><<<(unsigned)blocks, 256, 0, st>>>(m, aii, ajj, aij, hyp, tol, tthresh, skip,
+                                                                   t, c, status, code);
+    else
+        pair_params_kernel<false><<<(unsigned)blocks, 256, 0, st>>>(m, aii, ajj, aij, hyp, tol, tthresh, skip,
+                                                                    t, c, status, code);
     return hipGetLastError();
 }
 

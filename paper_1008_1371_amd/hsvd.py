@@ -91,13 +91,14 @@ def lib():
                              vp, vp, ctypes.POINTER(hsvd_info)]
     L.hsvd_pair_params.argtypes = [vp, ctypes.c_longlong, vp, vp, vp, vp, dp, dp, vp, vp, vp, vp,
                                    vp]
+    L.hsvd_block_pair_params.argtypes = L.hsvd_pair_params.argtypes
     L.hsvd_pivot_trace.argtypes = [vp, ip, ip, ip, vp]
     L.hsvd_sort_diag.argtypes = [vp, ip, ip, vp, vp]
     L.hsvd_block_trace.argtypes = [vp, ip, ip, ip, ip, vp]
     L.hsvd_solve_batched.argtypes = [vp, ip, vp, vp, vp, vp, vp, ctypes.POINTER(hsvd_params), vp, vp,
                                      vp, vp, vp, vp, ctypes.POINTER(hsvd_info)]
     L.hsvd_version.restype = ctypes.c_char_p
-    for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_pair_params",
+    for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_pair_params", "hsvd_block_pair_params",
                  "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_block_trace", "hsvd_solve_batched"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -271,7 +272,7 @@ def hsvd_solve_batched(ctx: Context, ns, ps, G_packed, offs, voffs, params: hsvd
                 info=info.as_dict())
 
 
-def hsvd_pair_params(ctx: Context, aii, ajj, aij, hyp, tol: float, t_thresh: float):
+def hsvd_pair_params(ctx: Context, aii, ajj, aij, hyp, tol: float, t_thresh: float, block=False):
     import torch
     m = aii.numel()
     dev = aii.device
@@ -280,9 +281,9 @@ def hsvd_pair_params(ctx: Context, aii, ajj, aij, hyp, tol: float, t_thresh: flo
     code = torch.empty(m, dtype=torch.int32, device=dev)
     t = torch.empty(m, dtype=torch.float64, device=dev)
     c = torch.empty(m, dtype=torch.float64, device=dev)
-    _check(lib().hsvd_pair_params(ctx.handle, m, _ptr(aii), _ptr(ajj), _ptr(aij), _ptr(hyp),
-                                  float(tol), float(t_thresh), _ptr(skip), _ptr(t), _ptr(c),
-                                  _ptr(status), _ptr(code)), "hsvd_pair_params")
+    fn = lib().hsvd_block_pair_params if block else lib().hsvd_pair_params
+    _check(fn(ctx.handle, m, _ptr(aii), _ptr(ajj), _ptr(aij), _ptr(hyp), float(tol), float(t_thresh),
+              _ptr(skip), _ptr(t), _ptr(c), _ptr(status), _ptr(code)), "hsvd_pair_params")
     return dict(skip=skip, t=t, c=c, status=status, code=code)
 
 
