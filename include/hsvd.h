@@ -123,6 +123,16 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p,
                        const hsvd_params *prm, double *sigma, double *U, int ldu,
                        double *V, int ldv, double *lambda, int *perm, hsvd_info *info);
 
+/* As hsvd_solve for a signature given in any order: jsig (device, n signed
+ * chars, each +1 or -1) is J's diagonal in the column order of G.  The columns
+ * are stably partitioned (+1 first), solved, and the outputs mapped back:
+ * sigma, U columns and lambda in the input column order, V = P V_p P^T (so
+ * G V = U Sigma and V^T J V = J with this J), perm as physical input columns.
+ * Errors: HSVD_E_INVAL also for an entry other than +-1.  Synchronises. */
+hsvd_status hsvd_solve_j(hsvd_ctx *ctx, const double *G, int lda, int n, const signed char *jsig,
+                         const hsvd_params *prm, double *sigma, double *U, int ldu, double *V, int ldv,
+                         double *lambda, int *perm, hsvd_info *info);
+
 /* Batched solves: `batch` independent problems G_k (n[k] x n[k], 1 <= n[k] <= 1024,
  * J_k = diag(I_p[k], -I_{n[k]-p[k]})), each solved as by hsvd_solve with the block
  * path (FP64) and its own tolerance (prm->tol <= 0: 1e-15 n[k]) and stop rule.

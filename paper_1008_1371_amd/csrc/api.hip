@@ -21,6 +21,8 @@ struct hsvd_ctx {
     hipStream_t stream = nullptr;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    void *aux = nullptr;                     // buffers of hsvd_solve_j (outside the solver's workspace)
+    size_t aux_bytes = 0;
     hsvd::Ctl *host_ctl = nullptr;           // pinned
     std::vector<hipEvent_t> events;          // reusable timing events
     rocblas_handle blas = nullptr;           // created on the first mixed solve
@@ -67,11 +69,11 @@ Layout make_layout(int n, int r, int ldg, bool want_v, int pairs, int splits, in
     L.mixed = mixed;
     const size_t mat = (size_t)ldg * r;
     L.off_G32 = take(mixed ? sizeof(float) * mat : 0);
-    L.off_V32 = take(mixed && want_v ? sizeof(float) * mat : 0);
+    L.off_V32 = take(mixed ? sizeof(float) * mat : 0);
     L.off_P32 = take(mixed ? sizeof(float) * (size_t)pairs * splits * bb : 0);
     L.off_W32 = take(mixed ? sizeof(float) * (size_t)pairs * bb : 0);
-    L.off_T1 = take(mixed && want_v ? sizeof(double) * mat : 0);
-    L.off_T2 = take(mixed && want_v ? sizeof(double) * mat : 0);
+    L.off_T1 = take(mixed ? sizeof(double) * mat : 0);
+    L.off_T2 = take(mixed ? sizeof(double) * mat : 0);
     L.bytes = o;
     return L;
 }
@@ -193,6 +195,7 @@ hsvd_status hsvd_destroy(hsvd_ctx *ctx)
     hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->events) hipEventDestroy(e);
     if (ctx->ws) hipFree(ctx->ws);
+    if (ctx->aux) hipFree(ctx->aux);
     if (ctx->host_ctl) hipHostFree(ctx->host_ctl);
     if (ctx->blas) rocblas_destroy_handle(ctx->blas);
     delete ctx;
@@ -284,6 +287,8 @@ hsvd_status reorthogonalise(hsvd_ctx *ctx, const Workspace &w, int r, int p, int
     iters = 0;
     resid = 1.0;
     double prev = 2.0;
+    // residual at the level of the rounding of the products themselves
+    const double floor_ = 16.0 * r * 0x1p-53;
     for (int it = 0; it < 6; ++it) {
         HSVD_TRY(launch_rowsign(st, w.V, w.T1, p, ldg, r));  // T1 = J X
         BLAS_TRY(rocblas_dgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, r, r, r, &one, w.V,
@@ -294,9 +299,10 @@ hsvd_status reorthogonalise(hsvd_ctx *ctx, const Workspace &w, int r, int p, int
         HSVD_TRY(hipMemcpyAsync(&ctx->host_ctl->nsres, &w.ctl->nsres, sizeof(double), hipMemcpyDeviceToHost, st));
         HSVD_TRY(hipStreamSynchronize(st));
         resid = ctx->host_ctl->nsres;
-        // stop once X is J-orthogonal to working accuracy (the residual no
-        // longer falls quadratically) -- the last correction is not applied
-        if (!(resid < 1.0) || (iters > 0 && resid > 0.25 * prev)) break;
+        // stop once X is J-orthogonal to working accuracy (residual at the
+        // rounding floor, or no longer falling quadratically) -- that last
+        // correction is not applied
+        if (!(resid < 1.0) || resid <= floor_ || (iters > 0 && resid > 0.25 * prev)) break;
         BLAS_TRY(rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, r, r, r, &one, w.V, ldg,
                                w.T2, ldg, &zero, w.T1, ldg));  // T1 = X T2
         HSVD_TRY(launch_copy(st, w.T1, w.V, ldg, r));
@@ -362,7 +368,9 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
                                       : (prm.ordering == HSVD_ORD_MODMOD ? r : r - 1);
 
     HSVD_TRY(hipSetDevice(ctx->device));
-    const Layout L = make_layout(n, r, ldg, want_v, pairs, splits, block ? 2 * b : 0, mixed);
+    // the mixed path needs V (to re-orthogonalise and form G X) even when it is not returned
+    const bool acc_v = want_v || mixed;
+    const Layout L = make_layout(n, r, ldg, acc_v, pairs, splits, block ? 2 * b : 0, mixed);
     hsvd_status s = ensure_ws(ctx, L.bytes);
     if (s != HSVD_OK) return s;
     const int nev = block ? 4 + 4 * steps_per_sweep : 4;
@@ -444,10 +452,10 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
         bool finished = false;
         if (mixed) {
             // FP32 sweeps on FP32 copies of G and V.
-            HSVD_TRY(launch_to_fp32(st, w.G, w.G32, want_v ? w.V32 : nullptr, ldg, r));
+            HSVD_TRY(launch_to_fp32(st, w.G, w.G32, w.V32, ldg, r));
             BlockArgsT<float> fa;
             fa.G = w.G32;
-            fa.V = want_v ? w.V32 : nullptr;
+            fa.V = w.V32;
             fa.ldg = ldg;
             fa.r = r;
             fa.p = p;
@@ -486,14 +494,9 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             if (status == HSVD_OK) {
                 // back to FP64: X = J-orthogonalised V32, G1 = G X, V0 = X
                 HSVD_TRY(hipEventRecord(ev[2], st));
-                if (want_v) {
-                    HSVD_TRY(launch_promote(st, w.V32, w.V, ldg, r));
-                    s = reorthogonalise(ctx, w, r, p, ldg, ns_iters, ns_resid);
-                    if (s != HSVD_OK) return s;
-                } else {
-                    // without V the FP32 phase only serves as a preconditioner of G
-                    HSVD_TRY(launch_promote(st, w.G32, w.G, ldg, r));
-                }
+                HSVD_TRY(launch_promote(st, w.V32, w.V, ldg, r));
+                s = reorthogonalise(ctx, w, r, p, ldg, ns_iters, ns_resid);
+                if (s != HSVD_OK) return s;
                 HSVD_TRY(hipEventRecord(ev[3], st));
                 HSVD_TRY(hipStreamSynchronize(st));
                 float ms = 0.f;
@@ -507,7 +510,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
         if (status == HSVD_OK) {
             BlockArgs ba;
             ba.G = w.G;
-            ba.V = want_v ? w.V : nullptr;
+            ba.V = want_v ? w.V : nullptr;  // the mixed path keeps V only when it is returned
             ba.ldg = ldg;
             ba.r = r;
             ba.p = p;
@@ -594,7 +597,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
                 info->kernel_bytes[kb + 2] = acts * 2.0 * esz * b2 * rows * vmul;
                 info->kernel_flops[kb + 2] = acts * 2.0 * b2 * b2 * rows * vmul;
             }
-            if (mixed && want_v) {
+            if (mixed) {
                 const double rr = (double)r;
                 info->kernel_flops[HSVD_K_REORTH] = (2.0 * ns_iters + 1.0 + 1.0) * 2.0 * rr * rr * rr;
                 info->kernel_bytes[HSVD_K_REORTH] = (2.0 * ns_iters + 2.0) * 3.0 * 8.0 * rr * rr;
@@ -617,6 +620,62 @@ size_t take_bytes(size_t &o, size_t bytes)
 }
 
 }  // namespace
+
+extern "C" hsvd_status hsvd_solve_j(hsvd_ctx *ctx, const double *G, int lda, int n, const signed char *jsig,
+                                    const hsvd_params *prm_in, double *sigma, double *U, int ldu, double *V,
+                                    int ldv, double *lambda, int *perm, hsvd_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    if (!ctx || !G || !jsig || !sigma || n < 1 || lda < n) return HSVD_E_INVAL;
+    if (U && ldu < n) return HSVD_E_INVAL;
+    if (V && ldv < n) return HSVD_E_INVAL;
+    HSVD_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    std::vector<signed char> hj(n);
+    HSVD_TRY(hipMemcpyAsync(hj.data(), jsig, n, hipMemcpyDeviceToHost, st));
+    HSVD_TRY(hipStreamSynchronize(st));
+    std::vector<int> pi;
+    pi.reserve(n);
+    for (int c = 0; c < n; ++c) {
+        if (hj[c] != 1 && hj[c] != -1) return HSVD_E_INVAL;
+        if (hj[c] == 1) pi.push_back(c);
+    }
+    const int p = (int)pi.size();
+    for (int c = 0; c < n; ++c)
+        if (hj[c] == -1) pi.push_back(c);
+    // aux: pi, Gp, sigma_p, lambda_p, perm_p, U_p, V_p
+    size_t o = 0;
+    const size_t nn = (size_t)n * n;
+    const size_t o_pi = take_bytes(o, sizeof(int) * n), o_Gp = take_bytes(o, sizeof(double) * nn);
+    const size_t o_s = take_bytes(o, sizeof(double) * n), o_l = take_bytes(o, sizeof(double) * n);
+    const size_t o_pm = take_bytes(o, sizeof(int) * n), o_U = take_bytes(o, sizeof(double) * nn);
+    const size_t o_V = take_bytes(o, sizeof(double) * nn);
+    if (ctx->aux_bytes < o) {
+        if (ctx->aux) {
+            HSVD_TRY(hipStreamSynchronize(st));
+            hipFree(ctx->aux);
+            ctx->aux = nullptr;
+            ctx->aux_bytes = 0;
+        }
+        if (hipMalloc(&ctx->aux, o) != hipSuccess) return HSVD_E_NOMEM;
+        ctx->aux_bytes = o;
+    }
+    char *a = static_cast<char *>(ctx->aux);
+    int *dpi = reinterpret_cast<int *>(a + o_pi);
+    double *Gp = reinterpret_cast<double *>(a + o_Gp);
+    double *sp = reinterpret_cast<double *>(a + o_s), *lp = reinterpret_cast<double *>(a + o_l);
+    int *pmp = reinterpret_cast<int *>(a + o_pm);
+    double *Up = reinterpret_cast<double *>(a + o_U), *Vp = reinterpret_cast<double *>(a + o_V);
+    HSVD_TRY(hipMemcpyAsync(dpi, pi.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    HSVD_TRY(launch_gather_cols(st, G, lda, dpi, Gp, n));
+    const hsvd_status s = hsvd_solve(ctx, Gp, n, n, p, prm_in, sp, U ? Up : nullptr, n, V ? Vp : nullptr, n,
+                                     lp, pmp, info);
+    if (s == HSVD_E_INVAL || s == HSVD_E_DEVICE || s == HSVD_E_NOMEM) return s;
+    HSVD_TRY(launch_scatter_outputs(st, dpi, n, sp, U ? Up : nullptr, V ? Vp : nullptr, lp, pmp, sigma, U, ldu,
+                                    V, ldv, lambda, perm));
+    HSVD_TRY(hipStreamSynchronize(st));
+    return s;
+}
 
 extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n, const int *p,
                                           const long long *off, const long long *voff, const double *G,

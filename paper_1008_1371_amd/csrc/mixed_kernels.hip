@@ -77,6 +77,58 @@ __global__ __launch_bounds__(256) void copy_kernel(const double *__restrict__ sr
         dst[(size_t)c * ldg + row] = row < r ? src[(size_t)c * ldg + row] : 0.0;
 }
 
+// Column gather Gp[:, k] = G[:, pi[k]] (n x n, leading dimensions ld_in / n).
+__global__ __launch_bounds__(256) void gather_cols_kernel(const double *__restrict__ G, int lda,
+                                                          const int *__restrict__ pi, double *__restrict__ Gp,
+                                                          int n)
+{
+    const int k = blockIdx.x;
+    const double *src = G + (size_t)pi[k] * lda;
+    for (int row = threadIdx.x; row < n; row += 256) Gp[(size_t)k * n + row] = src[row];
+}
+
+// Outputs of the partitioned solve back to the input column order:
+// sigma[pi[k]], lambda[pi[k]], U[:, pi[k]] from column k, V[pi[i], pi[k]] from
+// (i, k), perm[q] = pi[perm_p[q]].  grid n
+__global__ __launch_bounds__(256) void scatter_outputs_kernel(const int *__restrict__ pi, int n,
+                                                              const double *__restrict__ sp,
+                                                              const double *__restrict__ Up,
+                                                              const double *__restrict__ Vp,
+                                                              const double *__restrict__ lp,
+                                                              const int *__restrict__ permp,
+                                                              double *__restrict__ sigma,
+                                                              double *__restrict__ U, int ldu,
+                                                              double *__restrict__ V, int ldv,
+                                                              double *__restrict__ lambda, int *__restrict__ perm)
+{
+    const int k = blockIdx.x;
+    const int c = pi[k];
+    if (threadIdx.x == 0) {
+        sigma[c] = sp[k];
+        if (lambda) lambda[c] = lp[k];
+        if (perm) perm[k] = pi[permp[k]];
+    }
+    for (int row = threadIdx.x; row < n; row += 256) {
+        if (U) U[(size_t)c * ldu + row] = Up[(size_t)k * n + row];
+        if (V) V[(size_t)c * ldv + pi[row]] = Vp[(size_t)k * n + row];
+    }
+}
+
+hipError_t launch_gather_cols(hipStream_t st, const double *G, int lda, const int *pi, double *Gp, int n)
+{
+    gather_cols_kernel<<<n, 256, 0, st>>>(G, lda, pi, Gp, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_outputs(hipStream_t st, const int *pi, int n, const double *sp, const double *Up,
+                                  const double *Vp, const double *lp, const int *permp, double *sigma, double *U,
+                                  int ldu, double *V, int ldv, double *lambda, int *perm)
+{
+    scatter_outputs_kernel<<<n, 256, 0, st>>>(pi, n, sp, Up, Vp, lp, permp, sigma, U, ldu, V, ldv, lambda,
+                                              perm);
+    return hipGetLastError();
+}
+
 hipError_t launch_to_fp32(hipStream_t st, const double *G, float *G32, float *V32, int ldg, int r)
 {
     to_fp32_kernel<<<r, 256, 0, st>>>(G, G32, V32, ldg, r);

@@ -92,13 +92,16 @@ def lib():
     L.hsvd_pair_params.argtypes = [vp, ctypes.c_longlong, vp, vp, vp, vp, dp, dp, vp, vp, vp, vp,
                                    vp]
     L.hsvd_block_pair_params.argtypes = L.hsvd_pair_params.argtypes
+    L.hsvd_solve_j.argtypes = [vp, vp, ip, ip, vp, ctypes.POINTER(hsvd_params), vp, vp, ip, vp, ip,
+                               vp, vp, ctypes.POINTER(hsvd_info)]
     L.hsvd_pivot_trace.argtypes = [vp, ip, ip, ip, vp]
     L.hsvd_sort_diag.argtypes = [vp, ip, ip, vp, vp]
     L.hsvd_block_trace.argtypes = [vp, ip, ip, ip, ip, vp]
     L.hsvd_solve_batched.argtypes = [vp, ip, vp, vp, vp, vp, vp, ctypes.POINTER(hsvd_params), vp, vp,
                                      vp, vp, vp, vp, ctypes.POINTER(hsvd_info)]
     L.hsvd_version.restype = ctypes.c_char_p
-    for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_pair_params", "hsvd_block_pair_params",
+    for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_solve_j", "hsvd_pair_params",
+                 "hsvd_block_pair_params",
                  "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_block_trace", "hsvd_solve_batched"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -221,6 +224,31 @@ def hsvd_solve(ctx: Context, G, p: int, params: hsvd_params | None = None, *, wa
                       ctypes.byref(info))
     if check and st not in (OK,):
         raise HsvdError(st, "hsvd_solve")
+    return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, perm=perm, info=info.as_dict())
+
+
+def hsvd_solve_j(ctx: Context, G, jsig, params: hsvd_params | None = None, *, check=True):
+    """As hsvd_solve with J's diagonal given in any order: jsig is an int8
+    CUDA tensor of +-1 entries, one per column of G."""
+    import torch
+    L = lib()
+    n = G.shape[0]
+    assert G.shape == (n, n) and G.dtype == torch.float64 and G.is_cuda
+    assert jsig.dtype == torch.int8 and jsig.numel() == n
+    prm = params if params is not None else hsvd_default_params()
+    Gc, lda = _colmajor(G)
+    dev = G.device
+    sigma = torch.empty(n, dtype=torch.float64, device=dev)
+    U = _new_colmajor(n, dev, torch.float64)
+    V = _new_colmajor(n, dev, torch.float64) if prm.want_v else None
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    info = hsvd_info()
+    st = L.hsvd_solve_j(ctx.handle, _ptr(Gc), lda, n, _ptr(jsig.contiguous()), ctypes.byref(prm),
+                        _ptr(sigma), _ptr(U), U.stride(1), _ptr(V), V.stride(1) if V is not None else n,
+                        _ptr(lam), _ptr(perm), ctypes.byref(info))
+    if check and st != OK:
+        raise HsvdError(st, "hsvd_solve_j")
     return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, perm=perm, info=info.as_dict())
 
 
