@@ -56,6 +56,8 @@ typedef struct {
     int max_sweeps;  /* <= 0: 100                                                        */
     double tol;      /* threshold of the relative orthogonality test (eq. 2.3); <= 0: 1e-15 n */
     double t_thresh; /* T of eq. (4.2); <= 0: sqrt(tol) / 2 (Sec. 2)                     */
+    int graph;       /* hsvd_solve_batched: 1 = capture one sweep of a group as a HIP
+                        graph and replay it (no per-kernel timing in hsvd_info)        */
 } hsvd_params;
 
 /* Kernel classes timed in hsvd_info (index into the kernel_* arrays). */
@@ -102,7 +104,7 @@ hsvd_status hsvd_init(hsvd_ctx **ctx, int device, void *hip_stream);
 hsvd_status hsvd_destroy(hsvd_ctx *ctx);
 
 /* Fills *prm with the defaults: FP64, AUTO, modified modulus, sort on, V on,
-   max_sweeps 100, tol and t_thresh from n at solve time. */
+   max_sweeps 100, tol and t_thresh from n at solve time, graph replay on. */
 void hsvd_default_params(hsvd_params *prm);
 
 /* One-sided Jacobi HSVD of a square G (Sec. 2 and Sec. 4, Algs. 4.1-4.5).

@@ -26,6 +26,8 @@ struct hsvd_ctx {
     hsvd::Ctl *host_ctl = nullptr;           // pinned
     std::vector<hipEvent_t> events;          // reusable timing events
     rocblas_handle blas = nullptr;           // created on the first mixed solve
+    hipStream_t cap = nullptr;               // non-blocking stream for graph capture (default priority)
+    hipEvent_t join = nullptr;               // orders the capture stream with the caller's stream
 };
 
 namespace hsvd {
@@ -164,6 +166,7 @@ void hsvd_default_params(hsvd_params *prm)
     prm->max_sweeps = 100;
     prm->tol = 0.0;
     prm->t_thresh = 0.0;
+    prm->graph = 1;
 }
 
 hsvd_status hsvd_init(hsvd_ctx **out, int device, void *hip_stream)
@@ -198,6 +201,8 @@ hsvd_status hsvd_destroy(hsvd_ctx *ctx)
     if (ctx->aux) hipFree(ctx->aux);
     if (ctx->host_ctl) hipHostFree(ctx->host_ctl);
     if (ctx->blas) rocblas_destroy_handle(ctx->blas);
+    if (ctx->cap) hipStreamDestroy(ctx->cap);
+    if (ctx->join) hipEventDestroy(ctx->join);
     delete ctx;
     return HSVD_OK;
 }
@@ -833,39 +838,84 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         ba.tthvec = g.tth;
         long long gstep = 0;
         int gsweeps = 0;
-        for (int sw = 0; sw < max_sweeps; ++sw) {
+        int *host_active = &ctx->host_ctl->code;  // pinned scratch for the count of running problems
+        // one sweep: the outer steps, the kept diagonal, the sort, the stop rule
+        auto enqueue_sweep = [&](hipStream_t q, bool timed) -> hipError_t {
             for (int k = 0; k < steps_per_sweep; ++k, ++gstep) {
                 ba.step = k;
                 ba.S_in = S2 + (gstep & 1) * pairs;
                 ba.S_out = S2 + ((gstep + 1) & 1) * pairs;
                 hipEvent_t *e = ev + 4 + 4 * k;
-                HSVD_TRY(hipEventRecord(e[0], st));
-                HSVD_TRY(launch_block_gram<double>(st, ba));
-                HSVD_TRY(hipEventRecord(e[1], st));
-                HSVD_TRY(launch_block_inner<double>(st, ba));
-                HSVD_TRY(hipEventRecord(e[2], st));
-                HSVD_TRY(launch_block_update<double>(st, ba));
-                HSVD_TRY(hipEventRecord(e[3], st));
+                hipError_t er;
+                if (timed && (er = hipEventRecord(e[0], q)) != hipSuccess) return er;
+                if ((er = launch_block_gram<double>(q, ba)) != hipSuccess) return er;
+                if (timed && (er = hipEventRecord(e[1], q)) != hipSuccess) return er;
+                if ((er = launch_block_inner<double>(q, ba)) != hipSuccess) return er;
+                if (timed && (er = hipEventRecord(e[2], q)) != hipSuccess) return er;
+                if ((er = launch_block_update<double>(q, ba)) != hipSuccess) return er;
+                if (timed && (er = hipEventRecord(e[3], q)) != hipSuccess) return er;
             }
-            for (int q = 0; q < 3; ++q) klaunch[HSVD_K_BLOCK_GRAM + q] += steps_per_sweep;
+            hipError_t er;
+            if ((er = launch_batch_colnorm(q, g, false)) != hipSuccess) return er;
+            if (prm.sort && (er = launch_batch_sort(q, g)) != hipSuccess) return er;
+            if ((er = launch_batch_reduce_decide(q, g)) != hipSuccess) return er;
+            return hipMemcpyAsync(host_active, g.active_count, sizeof(int), hipMemcpyDeviceToHost, q);
+        };
+        hipGraphExec_t exec = nullptr;
+        hipGraph_t graph = nullptr;
+        hipStream_t q = st;
+        if (prm.graph) {
+            // steps_per_sweep is even for the modified modulus ordering, so the
+            // stepper's double buffer is in the same phase at every sweep and
+            // one captured sweep serves them all (round-robin keeps no state)
+            if (!ctx->cap) HSVD_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+            if (!ctx->join) HSVD_TRY(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
+            q = ctx->cap;
+            HSVD_TRY(hipEventRecord(ctx->join, st));
+            HSVD_TRY(hipStreamWaitEvent(q, ctx->join, 0));
+            HSVD_TRY(hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal));
+            const long long g0 = gstep;
+            const hipError_t ce = enqueue_sweep(q, false);
+            gstep = g0;
+            hipError_t ee = hipStreamEndCapture(q, &graph);
+            if (ce != hipSuccess || ee != hipSuccess) {
+                if (graph) hipGraphDestroy(graph);
+                return HSVD_E_DEVICE;
+            }
+            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                hipGraphDestroy(graph);
+                return HSVD_E_DEVICE;
+            }
+        }
+        for (int sw = 0; sw < max_sweeps; ++sw) {
+            if (prm.graph) {
+                HSVD_TRY(hipGraphLaunch(exec, q));
+                gstep += steps_per_sweep;
+            } else {
+                HSVD_TRY(enqueue_sweep(q, true));
+            }
+            for (int qk = 0; qk < 3; ++qk) klaunch[HSVD_K_BLOCK_GRAM + qk] += steps_per_sweep;
             tot_steps += steps_per_sweep;
-            HSVD_TRY(launch_batch_colnorm(st, g, false));
-            if (prm.sort) HSVD_TRY(launch_batch_sort(st, g));
-            HSVD_TRY(launch_batch_reduce_decide(st, g));
-            int active = 0;
-            HSVD_TRY(hipMemcpyAsync(&ctx->host_ctl->code, g.active_count, sizeof(int), hipMemcpyDeviceToHost, st));
-            HSVD_TRY(hipStreamSynchronize(st));
-            active = ctx->host_ctl->code;
-            for (int k = 0; k < steps_per_sweep; ++k) {
-                hipEvent_t *e = ev + 4 + 4 * k;
-                for (int q = 0; q < 3; ++q) {
-                    float ms = 0.f;
-                    HSVD_TRY(hipEventElapsedTime(&ms, e[q], e[q + 1]));
-                    kms[HSVD_K_BLOCK_GRAM + q] += ms;
+            HSVD_TRY(hipStreamSynchronize(q));
+            const int active = *host_active;
+            if (!prm.graph) {
+                for (int k = 0; k < steps_per_sweep; ++k) {
+                    hipEvent_t *e = ev + 4 + 4 * k;
+                    for (int qk = 0; qk < 3; ++qk) {
+                        float ms = 0.f;
+                        HSVD_TRY(hipEventElapsedTime(&ms, e[qk], e[qk + 1]));
+                        kms[HSVD_K_BLOCK_GRAM + qk] += ms;
+                    }
                 }
             }
             ++gsweeps;
             if (active == 0) break;
+        }
+        if (prm.graph) {
+            hipGraphExecDestroy(exec);
+            hipGraphDestroy(graph);
+            HSVD_TRY(hipEventRecord(ctx->join, q));
+            HSVD_TRY(hipStreamWaitEvent(st, ctx->join, 0));
         }
         HSVD_TRY(launch_batch_finalize(st, g, sigma, U, want_v ? V : nullptr, lambda));
         std::vector<int> hs(K), hsw(K);
