@@ -157,6 +157,20 @@ hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n, const int
                                double *U, double *V, double *lambda, int *status, int *sweeps,
                                hsvd_info *info);
 
+/* Autotuner.  Times the speed-only choices of the library on a seeded synthetic
+ * problem of order n (uniform entries in [-1, 1) from a counter-based hash,
+ * p = n/2; two sweeps per candidate): the path (pairwise, or block with the
+ * Gram's rows split for 256 / 512 / 1024 / 2048 workgroups per step).  The
+ * fastest is kept for n's size bucket (n rounded up to a power of two) in the
+ * context; later hsvd_solve calls with algo = HSVD_AUTO and block = 0 in that
+ * bucket use it.  A solve's result depends on the choice only through the
+ * pivot ordering of the chosen path and the Gram's summation order.  When the
+ * environment variable HSVD_AUTOTUNE_CACHE names a file, hsvd_init reads the
+ * table from it (JSON written by this call) and this call writes it back.
+ *   best_algo, best_wg   host, may be NULL: the chosen path and workgroup target.
+ * Errors: HSVD_E_INVAL (n < 2 or n > 16382).  Synchronises. */
+hsvd_status hsvd_autotune(hsvd_ctx *ctx, int n, int *best_algo, int *best_wg);
+
 /* ---- Diagnostics: the individual steps of the path on caller data ---- */
 
 /* Elementwise skip test (eq. 2.3), rotation parameters (Sec. 2: t = tan / tanh

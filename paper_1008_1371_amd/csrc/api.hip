@@ -6,6 +6,7 @@
 // host synchronisation inside a solve is one small copy of the control block
 // per sweep, which decides whether another sweep is launched.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -28,7 +29,61 @@ struct hsvd_ctx {
     rocblas_handle blas = nullptr;           // created on the first mixed solve
     hipStream_t cap = nullptr;               // non-blocking stream for graph capture (default priority)
     hipEvent_t join = nullptr;               // orders the capture stream with the caller's stream
+    struct Tune {
+        int valid = 0, algo = 0, wg = 0;
+    } tune[16];                              // autotuner choice per size bucket (log2 of n, rounded up)
 };
+
+namespace {
+
+int size_bucket(int n)
+{
+    int b = 0;
+    while ((1 << b) < n && b < 15) ++b;
+    return b;
+}
+
+void tune_load(hsvd_ctx *ctx)
+{
+    const char *path = getenv("HSVD_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char buf[4096];
+    const size_t len = fread(buf, 1, sizeof(buf) - 1, f);
+    fclose(f);
+    buf[len] = 0;
+    // entries written by tune_save: {"bucket": B, "algo": A, "wg": W}
+    for (const char *q = strstr(buf, "\"bucket\""); q; q = strstr(q + 1, "\"bucket\"")) {
+        int b = -1, a = 0, w = 0;
+        if (sscanf(q, "\"bucket\": %d, \"algo\": %d, \"wg\": %d", &b, &a, &w) == 3 && b >= 0 && b < 16 &&
+            (a == HSVD_PAIRWISE || a == HSVD_BLOCK) && w >= 0) {
+            ctx->tune[b].valid = 1;
+            ctx->tune[b].algo = a;
+            ctx->tune[b].wg = w;
+        }
+    }
+}
+
+void tune_save(const hsvd_ctx *ctx)
+{
+    const char *path = getenv("HSVD_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "w");
+    if (!f) return;
+    fprintf(f, "{\"library\": \"%s\", \"entries\": [", "hsvd-gfx950");
+    bool first = true;
+    for (int b = 0; b < 16; ++b) {
+        if (!ctx->tune[b].valid) continue;
+        fprintf(f, "%s\n  {\"bucket\": %d, \"algo\": %d, \"wg\": %d}", first ? "" : ",", b, ctx->tune[b].algo,
+                ctx->tune[b].wg);
+        first = false;
+    }
+    fprintf(f, "\n]}\n");
+    fclose(f);
+}
+
+}  // namespace
 
 namespace hsvd {
 
@@ -187,6 +242,7 @@ hsvd_status hsvd_init(hsvd_ctx **out, int device, void *hip_stream)
         return HSVD_E_DEVICE;
     }
     ctx->host_ctl = static_cast<Ctl *>(h);
+    tune_load(ctx);
     *out = ctx;
     return HSVD_OK;
 }
@@ -343,9 +399,13 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
     if (V && !prm.want_v) return HSVD_E_INVAL;
     const bool mixed = prm.precision == HSVD_MIXED;
     if (mixed && prm.algo == HSVD_PAIRWISE) return HSVD_E_INVAL;
-    // The block path needs at least two blocks of b columns; AUTO takes it from
-    // n >= 512, and always for the mixed path.
-    const bool block = mixed || prm.algo == HSVD_BLOCK || (prm.algo == HSVD_AUTO && n >= 512);
+    // The block path needs at least two blocks of b columns; AUTO takes the
+    // autotuner's choice for n's size bucket, else the block path from n >= 512;
+    // the mixed path always runs blocked.
+    const hsvd_ctx::Tune &tn = ctx->tune[size_bucket(n)];
+    const bool tuned = prm.algo == HSVD_AUTO && prm.block == 0 && tn.valid;
+    const bool block = mixed || prm.algo == HSVD_BLOCK ||
+                       (prm.algo == HSVD_AUTO && (tuned ? tn.algo == HSVD_BLOCK : n >= 512));
     const int b = block ? block_width() : 0;
     const int mult = block ? 2 * b : 2;
     const int r = (n + mult - 1) / mult * mult;  // eq. (4.1) bordering
@@ -361,9 +421,11 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
     const int pairs = nb / 2;
     int splits = 0, rows_per_split = 0;
     if (block) {
-        // split the Gram's rows so that about 1024 workgroups run per step
+        // split the Gram's rows so that about 1024 workgroups (or the tuned
+        // number) run per step
         const int chunks = ldg / 64;
-        int want = (1024 + pairs - 1) / pairs;
+        const int target = (tuned && tn.wg > 0) ? tn.wg : 1024;
+        int want = (target + pairs - 1) / pairs;
         want = want < 1 ? 1 : (want > chunks ? chunks : want);
         if (want > 32) want = 32;  // the inner kernels sum at most 32 partial Grams
         rows_per_split = (chunks + want - 1) / want * 64;
@@ -680,6 +742,69 @@ extern "C" hsvd_status hsvd_solve_j(hsvd_ctx *ctx, const double *G, int lda, int
                                     V, ldv, lambda, perm));
     HSVD_TRY(hipStreamSynchronize(st));
     return s;
+}
+
+extern "C" hsvd_status hsvd_autotune(hsvd_ctx *ctx, int n, int *best_algo, int *best_wg)
+{
+    if (!ctx || n < 2 || n > kMaxOrder - 2) return HSVD_E_INVAL;
+    HSVD_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    // synthetic problem and outputs in the auxiliary buffer
+    size_t o = 0;
+    const size_t nn = (size_t)n * n;
+    const size_t o_G = take_bytes(o, sizeof(double) * nn), o_s = take_bytes(o, sizeof(double) * n);
+    if (ctx->aux_bytes < o) {
+        if (ctx->aux) {
+            HSVD_TRY(hipStreamSynchronize(st));
+            hipFree(ctx->aux);
+            ctx->aux = nullptr;
+            ctx->aux_bytes = 0;
+        }
+        if (hipMalloc(&ctx->aux, o) != hipSuccess) return HSVD_E_NOMEM;
+        ctx->aux_bytes = o;
+    }
+    double *G = reinterpret_cast<double *>(static_cast<char *>(ctx->aux) + o_G);
+    double *sig = reinterpret_cast<double *>(static_cast<char *>(ctx->aux) + o_s);
+    HSVD_TRY(launch_synth(st, G, n, 0x5EEDull + (unsigned long long)n));
+    struct Cand {
+        int algo, wg;
+    } cands[5] = {{HSVD_PAIRWISE, 0}, {HSVD_BLOCK, 256}, {HSVD_BLOCK, 512}, {HSVD_BLOCK, 1024}, {HSVD_BLOCK, 2048}};
+    const int bucket = size_bucket(n);
+    const hsvd_ctx::Tune saved = ctx->tune[bucket];
+    double best = 1e300;
+    int ba = HSVD_BLOCK, bw = 1024;
+    for (const Cand &c : cands) {
+        hsvd_params prm;
+        hsvd_default_params(&prm);
+        prm.want_v = 1;
+        prm.max_sweeps = 2;
+        ctx->tune[bucket].valid = 1;
+        ctx->tune[bucket].algo = c.algo;
+        ctx->tune[bucket].wg = c.wg;
+        hsvd_info info;
+        double t = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {  // the first run also warms up
+            const hsvd_status s = hsvd_solve(ctx, G, n, n, n / 2, &prm, sig, nullptr, n, nullptr, n, nullptr,
+                                             nullptr, &info);
+            if (s != HSVD_OK && s != HSVD_E_NOCONV) {
+                ctx->tune[bucket] = saved;
+                return s;
+            }
+            t = info.ms_total;
+        }
+        if (t < best) {
+            best = t;
+            ba = c.algo;
+            bw = c.wg;
+        }
+    }
+    ctx->tune[bucket].valid = 1;
+    ctx->tune[bucket].algo = ba;
+    ctx->tune[bucket].wg = bw;
+    tune_save(ctx);
+    if (best_algo) *best_algo = ba;
+    if (best_wg) *best_wg = bw;
+    return HSVD_OK;
 }
 
 extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n, const int *p,

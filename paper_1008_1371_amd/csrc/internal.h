@@ -383,6 +383,7 @@ hipError_t launch_promote(hipStream_t st, const float *X32, double *X, int ldg, 
 hipError_t launch_rowsign(hipStream_t st, const double *X, double *Z, int p, int ldg, int r);
 hipError_t launch_ns_form(hipStream_t st, double *B, int p, int ldg, int r, Ctl *ctl);
 hipError_t launch_copy(hipStream_t st, const double *src, double *dst, int ldg, int r);
+hipError_t launch_synth(hipStream_t st, double *G, int n, unsigned long long seed);
 hipError_t launch_gather_cols(hipStream_t st, const double *G, int lda, const int *pi, double *Gp, int n);
 hipError_t launch_scatter_outputs(hipStream_t st, const int *pi, int n, const double *sp, const double *Up,
                                   const double *Vp, const double *lp, const int *permp, double *sigma, double *U,

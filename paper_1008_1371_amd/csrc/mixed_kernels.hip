@@ -129,6 +129,26 @@ hipError_t launch_scatter_outputs(hipStream_t st, const int *pi, int n, const do
     return hipGetLastError();
 }
 
+// Seeded synthetic matrix for the autotuner: uniform in [-1, 1) from the
+// splitmix64 hash of (seed, column-major index).
+__global__ __launch_bounds__(256) void synth_kernel(double *__restrict__ G, int n, unsigned long long seed)
+{
+    const int c = blockIdx.x;
+    for (int row = threadIdx.x; row < n; row += 256) {
+        unsigned long long z = seed + 0x9E3779B97F4A7C15ull * ((unsigned long long)c * n + row + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        G[(size_t)c * n + row] = (double)(z >> 11) * 0x1p-52 - 1.0;
+    }
+}
+
+hipError_t launch_synth(hipStream_t st, double *G, int n, unsigned long long seed)
+{
+    synth_kernel<<<n, 256, 0, st>>>(G, n, seed);
+    return hipGetLastError();
+}
+
 hipError_t launch_to_fp32(hipStream_t st, const double *G, float *G32, float *V32, int ldg, int r)
 {
     to_fp32_kernel<<<r, 256, 0, st>>>(G, G32, V32, ldg, r);

@@ -92,6 +92,7 @@ def lib():
     L.hsvd_pair_params.argtypes = [vp, ctypes.c_longlong, vp, vp, vp, vp, dp, dp, vp, vp, vp, vp,
                                    vp]
     L.hsvd_block_pair_params.argtypes = L.hsvd_pair_params.argtypes
+    L.hsvd_autotune.argtypes = [vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ip)]
     L.hsvd_solve_j.argtypes = [vp, vp, ip, ip, vp, ctypes.POINTER(hsvd_params), vp, vp, ip, vp, ip,
                                vp, vp, ctypes.POINTER(hsvd_info)]
     L.hsvd_pivot_trace.argtypes = [vp, ip, ip, ip, vp]
@@ -100,7 +101,8 @@ def lib():
     L.hsvd_solve_batched.argtypes = [vp, ip, vp, vp, vp, vp, vp, ctypes.POINTER(hsvd_params), vp, vp,
                                      vp, vp, vp, vp, ctypes.POINTER(hsvd_info)]
     L.hsvd_version.restype = ctypes.c_char_p
-    for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_solve_j", "hsvd_pair_params",
+    for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_solve_j", "hsvd_autotune",
+                 "hsvd_pair_params",
                  "hsvd_block_pair_params",
                  "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_block_trace", "hsvd_solve_batched"):
         getattr(L, name).restype = ctypes.c_int
@@ -225,6 +227,14 @@ def hsvd_solve(ctx: Context, G, p: int, params: hsvd_params | None = None, *, wa
     if check and st not in (OK,):
         raise HsvdError(st, "hsvd_solve")
     return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, perm=perm, info=info.as_dict())
+
+
+def hsvd_autotune(ctx: Context, n: int):
+    """Tunes the path and the Gram split for n's size bucket; returns (algo, wg)."""
+    a = ctypes.c_int()
+    w = ctypes.c_int()
+    _check(lib().hsvd_autotune(ctx.handle, int(n), ctypes.byref(a), ctypes.byref(w)), "hsvd_autotune")
+    return a.value, w.value
 
 
 def hsvd_solve_j(ctx: Context, G, jsig, params: hsvd_params | None = None, *, check=True):

@@ -108,3 +108,25 @@ def test_block_full_size_colscaled4096(hsvd_ctx):
     assert res["status"] == 0
     say("   info", {k: res["info"][k] for k in ("sweeps", "rotations", "ms_total")})
     pins.check_invariants(G, p, res, tol=1e-15 * 4096)
+
+
+def test_autotune_choice_used_and_cached(hsvd_ctx, tmp_path, monkeypatch):
+    """hsvd_autotune keeps the fastest path for the size bucket; AUTO solves in
+    that bucket use it; the JSON cache carries it to a new context."""
+    from paper_1008_1371_amd import hsvd as H
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("HSVD_AUTOTUNE_CACHE", str(cache))
+    with H.Context(0) as ctx:
+        algo, wg = H.hsvd_autotune(ctx, 384)
+        say("autotune 384 ->", algo, wg)
+        assert algo in (H.PAIRWISE, H.BLOCK)
+        G = W.gaussian(384, seed=2)
+        res = run_lib(ctx, G, 100)
+        assert res["status"] == 0
+        assert res["info"]["block"] == (32 if algo == H.BLOCK else 0)
+    assert cache.exists() and '"bucket": 9' in cache.read_text()
+    with H.Context(0) as ctx2:
+        res2 = run_lib(ctx2, G, 100)
+        assert res2["info"]["block"] == res["info"]["block"]
+        for k in ("sigma", "U", "V"):
+            assert np.array_equal(res[k], res2[k])
