@@ -74,7 +74,7 @@ def test_block_pair_params_close(hsvd_ctx):
     assert (np.abs(tg - tw) <= 8 * 2.0 ** -53 * np.abs(tw) * cond).all()
     cw, cg = want["c"][ok], g["c"][ok]
     assert (np.abs(cg - cw) <= 8 * 2.0 ** -53 * cw * cond ** 2).all()
-    assert (np.abs(g["t"][tie]) == 1.0).all()
+    assert (np.abs(np.abs(g["t"][tie]) - 1.0) <= 4 * 2.0 ** -53).all()
 
 
 @pytest.mark.parametrize("r", [2, 4, 8, 10, 130, 1024, 4096])
