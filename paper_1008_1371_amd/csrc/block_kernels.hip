@@ -359,80 +359,103 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
 // Slot coordinates: at inner step u slot s pairs local column L_s = s with
 // R_s(u) = b + ((s + u) mod b).  Thread (s1, s2) of 1024 holds the 2x2 block of
 // A_P with rows {L_s1, R_s1(u)} and columns {L_s2, R_s2(u)}, and the entries of W
-// in rows {s1, b + s1} and columns {L_s2, R_s2(u)}.  The diagonal thread (s, s)
-// holds slot s's pivot entries and computes its rotation; every block is then
-// updated in registers (A <- R^T A R, W <- W R).  Since R_s(u + 1) = R_{s+1}(u),
-// moving to the next inner step is a cyclic shift by one slot of the R-halves:
-// along s2 a lane shuffle within the 32-lane half-wave, along s1 an exchange
-// through LDS.  Blocks (s1, s2) and (s2, s1) apply their column and row
-// operations in mirrored order (columns first iff s1 <= s2), so the two stay
-// exact transposes and A stays exactly symmetric.
+// in rows {s1, b + s1} and columns {L_s2, R_s2(u)}.  Every block is updated in
+// registers (A <- R^T A R, W <- W R).  Since R_s(u + 1) = R_{s+1}(u), moving to
+// the next inner step is a cyclic shift by one slot of the R-halves: along s2 a
+// lane shuffle within the 32-lane half-wave, along s1 an exchange through LDS.
+// Blocks (s1, s2) and (s2, s1) apply their column and row operations in
+// mirrored order (columns first iff s1 <= s2), so the two stay exact
+// transposes and A stays exactly symmetric.
+//
+// The b rotations of an inner step are evaluated by the first wave alone (one
+// lane per slot), so the other waves do not issue that code: the threads that
+// hold the next step's pivot entries (a_LL at (s, s), a_LR at (s, s + 1),
+// a_RR at (s + 1, s + 1), before the shift) leave them in LDS next to the
+// row-shift exchange, and the rotations come back through LDS.  Two barriers
+// per inner step.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a)
 {
-    __shared__ double prm_t[kB], prm_c[kB], prm_h[kB], s_maxt[kB];
+    // A_P staging at the start, the row-shift exchange in the loop
+    __shared__ double buf[kB2 * kLd];
+    __shared__ double prm_t[kB], prm_c[kB], prm_h[kB];
     __shared__ int prm_rot[kB];
-    __shared__ double sh_rl[kB * kB], sh_rr[kB * kB];
-    __shared__ int s_code, s_rot, s_skip, s_rank;
+    __shared__ double pv_ll[kB], pv_rr[kB], pv_lr[kB];
     if (!bind_problem(a)) return;
     const int k = blockIdx.x;
     const int tid = threadIdx.x;
     const int s1 = tid >> 5, s2 = tid & 31;
     const int lane = tid & 63;
     const int2 IJ = outer_pair(a, k);
-    if (tid == 0) {
-        s_code = 0;
-        s_rot = 0;
-        s_skip = 0;
-        s_rank = 0;
-    }
 
-    // A_P from the partial Grams (upper triangle taken for both mirror entries)
-    const T *P = a.partial + (size_t)k * a.splits * (kB2 * kB2);
-    // two entries at a time, all their splits in flight, summed in split order
-    auto gram2 = [&](int x0, int y0, int x1, int y1, double &g0, double &g1) {
-        const int i0 = min(x0, y0) * kB2 + max(x0, y0);
-        const int i1 = min(x1, y1) * kB2 + max(x1, y1);
-        double v0[kMaxSplits / 2], v1[kMaxSplits / 2];
-        g0 = 0.0;
-        g1 = 0.0;
-        for (int base = 0; base < a.splits; base += kMaxSplits / 2) {
+    // A_P = sum of the partial Grams in split order.  Thread tid sums entries
+    // (x, y0 .. y0 + 3), x = tid / 16, y0 = 4 (tid % 16), of every split with
+    // vector loads; only the upper-triangular 16 x 16 tiles hold data.
+    {
+        typedef T v4 __attribute__((ext_vector_type(4)));
+        constexpr int kChunk = 8;
+        const int x = tid >> 4, y0 = (tid & 15) * 4;
+        if ((y0 >> 4) >= (x >> 4)) {
+            const T *P = a.partial + (size_t)k * a.splits * (kB2 * kB2) + x * kB2 + y0;
+            double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+            for (int base = 0; base < a.splits; base += kChunk) {
+                v4 v[kChunk];
 #pragma unroll
-            for (int q = 0; q < kMaxSplits / 2; ++q) {
-                const bool in = base + q < a.splits;
-                v0[q] = in ? (double)P[(size_t)(base + q) * (kB2 * kB2) + i0] : 0.0;
-                v1[q] = in ? (double)P[(size_t)(base + q) * (kB2 * kB2) + i1] : 0.0;
+                for (int q = 0; q < kChunk; ++q)
+                    v[q] = base + q < a.splits
+                               ? *reinterpret_cast<const v4 *>(P + (size_t)(base + q) * (kB2 * kB2))
+                               : v4{0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q)
+                    if (base + q < a.splits) {
+                        const bool first = base + q == 0;
+                        g0 = first ? (double)v[q][0] : g0 + (double)v[q][0];
+                        g1 = first ? (double)v[q][1] : g1 + (double)v[q][1];
+                        g2 = first ? (double)v[q][2] : g2 + (double)v[q][2];
+                        g3 = first ? (double)v[q][3] : g3 + (double)v[q][3];
+                    }
             }
-#pragma unroll
-            for (int q = 0; q < kMaxSplits / 2; ++q)
-                if (base + q < a.splits) {
-                    g0 = (base + q == 0) ? v0[q] : g0 + v0[q];
-                    g1 = (base + q == 0) ? v1[q] : g1 + v1[q];
-                }
+            double *row = buf + x * kLd + y0;
+            row[0] = g0;
+            row[1] = g1;
+            row[2] = g2;
+            row[3] = g3;
         }
-    };
-    double LL, LR, RL, RR;
-    gram2(s1, s2, s1, kB + s2, LL, LR);
-    gram2(kB + s1, s2, kB + s1, kB + s2, RL, RR);
-    double W0L = s1 == s2 ? 1.0 : 0.0, W0R = 0.0, W1L = 0.0, W1R = s1 == s2 ? 1.0 : 0.0;
-    const bool cols_first = s1 <= s2;
+    }
+    __syncthreads();
+    // entry (x, y) is read at (min, max) for both mirror positions
+    double LL = buf[min(s1, s2) * kLd + max(s1, s2)];
+    double LR = buf[s1 * kLd + kB + s2];
+    double RL = buf[s2 * kLd + kB + s1];
+    double RR = buf[(kB + min(s1, s2)) * kLd + kB + max(s1, s2)];
     const bool diag = s1 == s2;
-    int code = 0, nrot = 0, nskip = 0, rank = 0;
-    double maxt = 0.0;
+    if (diag) {
+        pv_ll[s1] = LL;
+        pv_rr[s1] = RR;
+        pv_lr[s1] = LR;
+    }
+    double W0L = diag ? 1.0 : 0.0, W0R = 0.0, W1L = 0.0, W1R = diag ? 1.0 : 0.0;
+    const bool cols_first = s1 <= s2;
+    const bool lr_owner = s2 == ((s1 + 1) & 31);          // holds a_LR of slot s1 for the next step
     const int shsrc = (lane & 32) | ((lane + 1) & 31);  // lane holding slot s2 + 1
     const int rowsrc = ((s1 + 1) & 31) * kB + s2;         // LDS cell of slot s1 + 1
+    double *sh_rl = buf, *sh_rr = buf + kB * kB;
+    int code = 0, nrot = 0, nskip = 0, rank = 0;
+    double maxt = 0.0;
+    __syncthreads();
 
     for (int u = 0; u < kB; ++u) {
-        if (diag) {
-            const int s = s1;
+        if (tid < kB) {
+            const int s = tid;
+            const double app = pv_ll[s], aqq = pv_rr[s], apq = pv_lr[s];
             // skip test and rotation evaluated side by side (independent
             // dependency chains), then selected
             const int pl = IJ.x * kB + s, pr = IJ.y * kB + ((s + u) & 31);
             const int hyp = ((pl < a.p) == (pr < a.p)) ? -1 : 1;
             double t, c;
-            const int bad = rotation_params_fast(LL, RR, LR, hyp, t, c);
-            const bool skip = rel_orthogonal(LL, RR, LR, a.tol);
+            const int bad = rotation_params_fast(app, aqq, apq, hyp, t, c);
+            const bool skip = rel_orthogonal(app, aqq, apq, a.tol);
             double h = 0.0;
             int rot = 0;
             if (skip) {
@@ -487,6 +510,12 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
             W1L = a1;
             W1R = b1;
         }
+        // pivots of the next inner step from their owners
+        if (diag) {
+            pv_ll[s1] = LL;
+            pv_rr[(s1 + 31) & 31] = RR;
+        }
+        if (lr_owner) pv_lr[s1] = LR;
         // shift the R halves by one slot: columns through a lane shuffle ...
         LR = __shfl(LR, shsrc, 64);
         RR = __shfl(RR, shsrc, 64);
@@ -505,24 +534,26 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
     Wg[s1 * kB2 + kB + s2] = (T)W0R;
     Wg[(kB + s1) * kB2 + s2] = (T)W1L;
     Wg[(kB + s1) * kB2 + kB + s2] = (T)W1R;
-    if (diag) {
-        if (code) atomicOr(&s_code, code);
-        if (nrot) atomicAdd(&s_rot, nrot);
-        if (nskip) atomicAdd(&s_skip, nskip);
-        if (rank) atomicOr(&s_rank, 1);
-        s_maxt[s1] = maxt;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        if (s_rank) atomicOr(&a.ctl->rank, 1);
-        double m = a.maxt[k];
-        for (int q = 0; q < kB; ++q) m = fmax(m, s_maxt[q]);
-        a.maxt[k] = m;
-        a.C[k] |= s_code;
-        a.nrot[k] += (unsigned)s_rot;
-        a.nskip[k] += (unsigned)s_skip;
-        a.nact[k] += s_rot > 0 ? 1u : 0u;
-        a.active[k] = s_rot > 0 ? 1 : 0;
+    if (tid < 64) {
+        // counters of the b slots, reduced within the first wave
+        unsigned rot_sum = (unsigned)nrot, skip_sum = (unsigned)nskip;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            code |= __shfl_xor(code, m, 64);
+            rank |= __shfl_xor(rank, m, 64);
+            rot_sum += __shfl_xor(rot_sum, m, 64);
+            skip_sum += __shfl_xor(skip_sum, m, 64);
+            maxt = fmax(maxt, __shfl_xor(maxt, m, 64));
+        }
+        if (tid == 0) {
+            if (rank) atomicOr(&a.ctl->rank, 1);
+            a.maxt[k] = fmax(a.maxt[k], maxt);
+            a.C[k] |= code;
+            a.nrot[k] += rot_sum;
+            a.nskip[k] += skip_sum;
+            a.nact[k] += rot_sum > 0 ? 1u : 0u;
+            a.active[k] = rot_sum > 0 ? 1 : 0;
+        }
     }
 }
 
