@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
             const double axx = A[x * kLd + x], ayy = A[y * kLd + y], axy = A[x * kLd + y];
             double t = 0.0, c = 1.0;
             int rot = 0;
-            if (rel_orthogonal(axx, ayy, axy, a.tol)) {
+            if (rel_orthogonal_sq(axx, ayy, axy, a.tol, a.tol * a.tol)) {
                 ++nskip;
             } else {
                 const int px_ = local_pos(x, IJ.x, IJ.y), py_ = local_pos(y, IJ.x, IJ.y);
@@ -357,35 +357,34 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
 // first of a sweep), register-resident.
 //
 // Slot coordinates: at inner step u slot s pairs local column L_s = s with
-// R_s(u) = b + ((s + u) mod b).  Thread (s1, s2) of 1024 holds the 2x2 block of
-// A_P with rows {L_s1, R_s1(u)} and columns {L_s2, R_s2(u)}, and the entries of W
-// in rows {s1, b + s1} and columns {L_s2, R_s2(u)}.  Every block is updated in
-// registers (A <- R^T A R, W <- W R).  Since R_s(u + 1) = R_{s+1}(u), moving to
-// the next inner step is a cyclic shift by one slot of the R-halves: along s2 a
-// lane shuffle within the 32-lane half-wave, along s1 an exchange through LDS.
+// R_s(u) = b + ((s + u) mod b).  The 2x2 block (s1, s2) of A_P has rows
+// {L_s1, R_s1(u)} and columns {L_s2, R_s2(u)}; it is held by thread (d, s) =
+// (tid / b, tid % b) with s1 = s, s2 = s + d mod b, i.e. by diagonals, so the
+// blocks that carry the pivots of the next inner step -- (s, s) and (s, s + 1)
+// -- all sit in the first wave.  Since R_s(u + 1) = R_{s+1}(u), moving to the
+// next inner step maps block (s1, s2) to
+//   LL <- LL,  LR <- LR(s1, s2 + 1),  RL <- RL(s1 + 1, s2),  RR <- RR(s1 + 1, s2 + 1):
+// a lane shuffle for RR (same diagonal) and an exchange through LDS for LR and
+// RL (neighbouring diagonals), double-buffered so that one barrier per inner
+// step suffices.  The first wave (raised priority) evaluates the b rotations
+// of the next step from its own registers right after its update and leaves
+// them in LDS (double-buffered as well) before that barrier.
+//
 // Blocks (s1, s2) and (s2, s1) apply their column and row operations in
 // mirrored order (columns first iff s1 <= s2), so the two stay exact
-// transposes and A stays exactly symmetric.
-//
-// The b rotations of an inner step are evaluated by the first wave alone (one
-// lane per slot), so the other waves do not issue that code: the threads that
-// hold the next step's pivot entries (a_LL at (s, s), a_LR at (s, s + 1),
-// a_RR at (s + 1, s + 1), before the shift) leave them in LDS next to the
-// row-shift exchange, and the rotations come back through LDS.  Two barriers
-// per inner step.
+// transposes and A stays exactly symmetric.  W, rows {s1, b + s1} by columns
+// {L_s2, R_s2(u)}, is held by thread (s1, s2) = (tid / b, tid % b) and shifts
+// along s2 by a lane shuffle.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a)
 {
-    // A_P staging at the start, the row-shift exchange in the loop
+    // A_P staging at the start, the two LR / RL exchange buffers in the loop
     __shared__ double buf[kB2 * kLd];
-    __shared__ double prm_t[kB], prm_c[kB], prm_h[kB];
-    __shared__ int prm_rot[kB];
-    __shared__ double pv_ll[kB], pv_rr[kB], pv_lr[kB];
+    __shared__ double4 prm[2][kB];  // (t, c, t or -t, rotated) of each slot
     if (!bind_problem(a)) return;
     const int k = blockIdx.x;
     const int tid = threadIdx.x;
-    const int s1 = tid >> 5, s2 = tid & 31;
     const int lane = tid & 63;
     const int2 IJ = outer_pair(a, k);
 
@@ -424,38 +423,39 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
         }
     }
     __syncthreads();
+    const int d = tid >> 5, s = tid & 31;
+    const int s1 = s, s2 = (s + d) & 31;
     // entry (x, y) is read at (min, max) for both mirror positions
     double LL = buf[min(s1, s2) * kLd + max(s1, s2)];
     double LR = buf[s1 * kLd + kB + s2];
     double RL = buf[s2 * kLd + kB + s1];
     double RR = buf[(kB + min(s1, s2)) * kLd + kB + max(s1, s2)];
-    const bool diag = s1 == s2;
-    if (diag) {
-        pv_ll[s1] = LL;
-        pv_rr[s1] = RR;
-        pv_lr[s1] = LR;
-    }
-    double W0L = diag ? 1.0 : 0.0, W0R = 0.0, W1L = 0.0, W1R = diag ? 1.0 : 0.0;
-    const bool cols_first = s1 <= s2;
-    const bool lr_owner = s2 == ((s1 + 1) & 31);          // holds a_LR of slot s1 for the next step
-    const int shsrc = (lane & 32) | ((lane + 1) & 31);  // lane holding slot s2 + 1
-    const int rowsrc = ((s1 + 1) & 31) * kB + s2;         // LDS cell of slot s1 + 1
-    double *sh_rl = buf, *sh_rr = buf + kB * kB;
+    const bool diag = d == 0;
+    const bool cf = s1 <= s2;
+    const int w1 = tid >> 5, w2 = tid & 31;  // W block of this thread
+    double W0L = w1 == w2 ? 1.0 : 0.0, W0R = 0.0, W1L = 0.0, W1R = w1 == w2 ? 1.0 : 0.0;
+    const int nxt = (lane & 32) | ((lane + 1) & 31);           // lane of (d, s + 1), resp. W column s2 + 1
+    const int lr_cell = (((d + 1) & 31) << 5) | s;             // thread (d + 1, s)
+    const int rl_cell = (((d + 31) & 31) << 5) | ((s + 1) & 31);  // thread (d - 1, s + 1)
+    double *const xlr = buf, *const xrl = buf + 2 * kB * kB;    // [2][b * b] each
+    // pivots of slot s (lanes 0 .. b-1 of the first wave)
+    double pll = LL, plr = LR, prr = RR;
     int code = 0, nrot = 0, nskip = 0, rank = 0;
     double maxt = 0.0;
+    const double tol2 = a.tol * a.tol;
+    if (tid < 64) __builtin_amdgcn_s_setprio(2);
     __syncthreads();
 
     for (int u = 0; u < kB; ++u) {
+        const int pb = u & 1;
         if (tid < kB) {
-            const int s = tid;
-            const double app = pv_ll[s], aqq = pv_rr[s], apq = pv_lr[s];
             // skip test and rotation evaluated side by side (independent
             // dependency chains), then selected
             const int pl = IJ.x * kB + s, pr = IJ.y * kB + ((s + u) & 31);
             const int hyp = ((pl < a.p) == (pr < a.p)) ? -1 : 1;
             double t, c;
-            const int bad = rotation_params_fast(app, aqq, apq, hyp, t, c);
-            const bool skip = rel_orthogonal(app, aqq, apq, a.tol);
+            const int bad = rotation_params_fast(pll, prr, plr, hyp, t, c);
+            const bool skip = rel_orthogonal_sq(pll, prr, plr, a.tol, tol2);
             double h = 0.0;
             int rot = 0;
             if (skip) {
@@ -473,67 +473,63 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
                 maxt = fmax(maxt, fabs(t));
                 h = hyp < 0 ? -t : t;
             }
-            prm_t[s] = t;
-            prm_c[s] = c;
-            prm_h[s] = h;
-            prm_rot[s] = rot;
+            prm[pb][s] = make_double4(t, c, h, rot ? 1.0 : 0.0);
         }
         __syncthreads();
-        const double t1 = prm_t[s1], c1 = prm_c[s1], h1 = prm_h[s1];
-        const double t2 = prm_t[s2], c2 = prm_c[s2], h2 = prm_h[s2];
-        // A block: rows (L_s1, R_s1) by slot s1, columns (L_s2, R_s2) by slot s2
-        if (cols_first) {
-            const double f00 = fma(h2, LR, LL) * c2, f01 = fma(t2, LL, LR) * c2;
-            const double f10 = fma(h2, RR, RL) * c2, f11 = fma(t2, RL, RR) * c2;
-            LL = fma(h1, f10, f00) * c1;
-            RL = fma(t1, f00, f10) * c1;
-            LR = fma(h1, f11, f01) * c1;
-            RR = fma(t1, f01, f11) * c1;
-        } else {
-            const double g00 = fma(h1, RL, LL) * c1, g10 = fma(t1, LL, RL) * c1;
-            const double g01 = fma(h1, RR, LR) * c1, g11 = fma(t1, LR, RR) * c1;
-            LL = fma(h2, g01, g00) * c2;
-            LR = fma(t2, g00, g01) * c2;
-            RL = fma(h2, g11, g10) * c2;
-            RR = fma(t2, g10, g11) * c2;
+        if (u > 0) {
+            // LR and RL of the shift to this step
+            LR = xlr[(pb ^ 1) * (kB * kB) + lr_cell];
+            RL = xrl[(pb ^ 1) * (kB * kB) + rl_cell];
         }
-        if (diag && prm_rot[s1]) {
+        // A block, rows by slot s1, columns by slot s2.  Columns first iff
+        // s1 <= s2; otherwise the same column-then-row sequence runs on the
+        // transposed block with the slots exchanged, which is the
+        // row-then-column order on the block itself.
+        const double4 pa = prm[pb][cf ? s2 : s1], pq = prm[pb][cf ? s1 : s2];
+        {
+            const double x01 = cf ? LR : RL, x10 = cf ? RL : LR;
+            const double f00 = fma(pa.z, x01, LL) * pa.y, f01 = fma(pa.x, LL, x01) * pa.y;
+            const double f10 = fma(pa.z, RR, x10) * pa.y, f11 = fma(pa.x, x10, RR) * pa.y;
+            const double y00 = fma(pq.z, f10, f00) * pq.y, y10 = fma(pq.x, f00, f10) * pq.y;
+            const double y01 = fma(pq.z, f11, f01) * pq.y, y11 = fma(pq.x, f01, f11) * pq.y;
+            LL = y00;
+            RR = y11;
+            LR = cf ? y01 : y10;
+            RL = cf ? y10 : y01;
+        }
+        if (diag && pa.w != 0.0) {
             LR = 0.0;
             RL = 0.0;
         }
-        // W columns (L_s2, R_s2) by slot s2
+        if (u + 1 < kB) {
+            xlr[pb * (kB * kB) + tid] = LR;
+            xrl[pb * (kB * kB) + tid] = RL;
+            RR = __shfl(RR, nxt, 64);
+            if (tid < 64) {
+                // next pivots: a_LL of (s, s), a_LR of (s, s + 1) (lane b + s),
+                // a_RR of (s + 1, s + 1) (just shifted in)
+                plr = __shfl(LR, kB + (lane & 31), 64);
+                pll = LL;
+                prr = RR;
+            }
+        }
+        // W <- W R on columns (L_w2, R_w2), then the shift of its R half
         {
-            const double a0 = fma(h2, W0R, W0L) * c2, b0 = fma(t2, W0L, W0R) * c2;
-            const double a1 = fma(h2, W1R, W1L) * c2, b1 = fma(t2, W1L, W1R) * c2;
+            const double4 pw = prm[pb][w2];
+            const double a0 = fma(pw.z, W0R, W0L) * pw.y, b0 = fma(pw.x, W0L, W0R) * pw.y;
+            const double a1 = fma(pw.z, W1R, W1L) * pw.y, b1 = fma(pw.x, W1L, W1R) * pw.y;
             W0L = a0;
-            W0R = b0;
             W1L = a1;
-            W1R = b1;
+            W0R = __shfl(b0, nxt, 64);
+            W1R = __shfl(b1, nxt, 64);
         }
-        // pivots of the next inner step from their owners
-        if (diag) {
-            pv_ll[s1] = LL;
-            pv_rr[(s1 + 31) & 31] = RR;
-        }
-        if (lr_owner) pv_lr[s1] = LR;
-        // shift the R halves by one slot: columns through a lane shuffle ...
-        LR = __shfl(LR, shsrc, 64);
-        RR = __shfl(RR, shsrc, 64);
-        W0R = __shfl(W0R, shsrc, 64);
-        W1R = __shfl(W1R, shsrc, 64);
-        // ... rows through LDS
-        sh_rl[tid] = RL;
-        sh_rr[tid] = RR;
-        __syncthreads();
-        RL = sh_rl[rowsrc];
-        RR = sh_rr[rowsrc];
     }
     // after b shifts the slots are back in natural order: R_s = b + s
     T *Wg = a.W + (size_t)k * (kB2 * kB2);
-    Wg[s1 * kB2 + s2] = (T)W0L;
-    Wg[s1 * kB2 + kB + s2] = (T)W0R;
-    Wg[(kB + s1) * kB2 + s2] = (T)W1L;
-    Wg[(kB + s1) * kB2 + kB + s2] = (T)W1R;
+    Wg[w1 * kB2 + w2] = (T)W0L;
+    Wg[w1 * kB2 + kB + w2] = (T)W0R;
+    Wg[(kB + w1) * kB2 + w2] = (T)W1L;
+    Wg[(kB + w1) * kB2 + kB + w2] = (T)W1R;
     if (tid < 64) {
         // counters of the b slots, reduced within the first wave
         unsigned rot_sum = (unsigned)nrot, skip_sum = (unsigned)nskip;

@@ -137,47 +137,57 @@ __device__ __forceinline__ double rsq_nr(double x)
 // the latency-bound inner solves of the block path.  With d = a_jj - a_ii,
 // w = 2 a_ij and S = a_ii + a_jj the smaller-magnitude roots are
 //   trig: t = sgn(d) w / (|d| + sqrt(d^2 + w^2)),          c = (1 + t^2)^(-1/2)
-//   hyp:  t = -w / (S + sqrt((S - |w|)(S + |w|))),          c = ((1 - t)(1 + t))^(-1/2)
+//   hyp:  t = -w / (S + sqrt((S - |w|)(S + |w|))),          c = (1 - t^2)^(-1/2)
 // (one square root, one reciprocal and one reciprocal square root instead of
 // three divisions and two or three square roots), rank failure iff S <= |w|.
-// Results agree with rotation_params to within a few ulps; for d = 0 the trig
-// case takes t = sgn(a_ij) (both signs annihilate a_ij).  Entries outside
-// [2^-480, 2^480], where the squares could leave the exponent range, use
-// rotation_params.
+// Both cases run as one select-driven sequence, q = X Y + Z with (X, Y, Z) =
+// (|d|, |d|, w^2) or (S - |w|, S + |w|, 0), so a wave holding pairs of both
+// kinds issues it once.  Results agree with rotation_params to within a few
+// ulps; for d = 0 the trig case takes t = sgn(a_ij) (both signs annihilate
+// a_ij).  Entries outside [2^-480, 2^480], where the squares could leave the
+// exponent range, use rotation_params.
+__device__ __forceinline__ bool fast_range(double aii, double ajj)
+{
+    const double lo = 0x1p-480, hi = 0x1p480;
+    return aii >= lo && aii <= hi && ajj >= lo && ajj <= hi;
+}
+
 __device__ __forceinline__ int rotation_params_fast(double aii, double ajj, double aij, int hyp, double &t,
                                                     double &c)
 {
-    const double lo = 0x1p-480, hi = 0x1p480;
-    if (!(aii >= lo && aii <= hi && ajj >= lo && ajj <= hi)) return rotation_params(aii, ajj, aij, hyp, t, c);
-    const double w = 2.0 * aij;
-    if (hyp < 0) {
-        const double d = ajj - aii;
-        const double r2 = fma(d, d, w * w);
-        const double s = r2 * rsq_nr(r2);
-        const double tt = (d < 0.0 ? -w : w) * rcp_nr(fabs(d) + s);
-        t = tt;
-        c = rsq_nr(fma(tt, tt, 1.0));
-        return 0;
-    }
-    const double S = aii + ajj, aw = fabs(w);
+    if (!fast_range(aii, ajj)) return rotation_params(aii, ajj, aij, hyp, t, c);
+    const bool trig = hyp < 0;
+    const double w = 2.0 * aij, aw = fabs(w);
+    const double d = ajj - aii, S = aii + ajj;
     const double m = S - aw;
-    if (!(m > 0.0)) {
-        t = 0.0;
-        c = 1.0;
-        return 1;
-    }
-    const double q = m * (S + aw);
+    const double X = trig ? fabs(d) : m, Y = trig ? fabs(d) : S + aw, Z = trig ? w * w : 0.0;
+    const double q = fma(X, Y, Z);
     const double s = q * rsq_nr(q);
-    const double tt = -w * rcp_nr(S + s);
-    t = tt;
-    c = rsq_nr((1.0 - tt) * (1.0 + tt));
-    return 0;
+    const double num = (trig && !(d < 0.0)) ? w : -w;
+    const double tt = num * rcp_nr((trig ? fabs(d) : S) + s);
+    const double cc = rsq_nr(fma(trig ? tt : -tt, tt, 1.0));
+    const int bad = (!trig && !(m > 0.0)) ? 1 : 0;
+    t = bad ? 0.0 : tt;
+    c = bad ? 1.0 : cc;
+    return bad;
 }
 
 // Relative orthogonality, eq. (2.3), strict: |a_ij| < tol sqrt(a_ii) sqrt(a_jj).
 __device__ __forceinline__ bool rel_orthogonal(double aii, double ajj, double aij, double tol)
 {
     return fabs(aij) < tol * (sqrt(aii) * sqrt(ajj));
+}
+
+// The same test squared, a_ij^2 < tol^2 a_ii a_jj (tol2 = tol^2), for the
+// block path: no square roots; equal to rel_orthogonal up to rounding at the
+// threshold itself.  Where the right-hand side is not a normal number (tiny
+// entries or tolerance) or the entries leave [2^-480, 2^480], rel_orthogonal
+// decides.
+__device__ __forceinline__ bool rel_orthogonal_sq(double aii, double ajj, double aij, double tol, double tol2)
+{
+    const double rhs = tol2 * (aii * ajj);
+    if (!fast_range(aii, ajj) || !(rhs >= 0x1p-1000)) return rel_orthogonal(aii, ajj, aij, tol);
+    return aij * aij < rhs;
 }
 
 // Eq. (4.2) code of one applied rotation, to be OR-ed into the slot's code.

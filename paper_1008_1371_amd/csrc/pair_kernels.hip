@@ -389,7 +389,9 @@ __global__ void pair_params_kernel(long long m, const double *__restrict__ aii,
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     double tt = 0.0, cc = 1.0;
-    int sk = rel_orthogonal(aii[k], ajj[k], aij[k], tol) ? 1 : 0;
+    const bool orth = kFast ? rel_orthogonal_sq(aii[k], ajj[k], aij[k], tol, tol * tol)
+                            : rel_orthogonal(aii[k], ajj[k], aij[k], tol);
+    int sk = orth ? 1 : 0;
     int stt = 0, cd = 0;
     if (!sk) {
         stt = kFast ? rotation_params_fast(aii[k], ajj[k], aij[k], hyp[k], tt, cc)
