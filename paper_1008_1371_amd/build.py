@@ -24,6 +24,9 @@ FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: keeps loop-carried accumulators
+    # from being copied between register files on every iteration
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I" + os.path.join(ROOT, "include"),
     "-Wall", "-Wno-unused-result",
 ]

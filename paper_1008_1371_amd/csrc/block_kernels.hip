@@ -111,15 +111,33 @@ __device__ __forceinline__ int local_pos(int x, int I, int J)
 // Gram: partial[k][split] = G_P(rows of split)^T G_P(rows of split)
 // ---------------------------------------------------------------------------
 // The Gram matrix is symmetric: only the 10 upper-triangular 16 x 16 tiles
-// (xt <= yt) of the 4 x 4 tiling are formed, 3, 3, 2 and 2 per wave.  Readers
-// take entry (min(x, y), max(x, y)).
-__constant__ int kGramTileX[4][3] = {{0, 0, 0}, {0, 1, 1}, {1, 2, 0}, {2, 3, 0}};
-__constant__ int kGramTileY[4][3] = {{0, 1, 2}, {3, 1, 2}, {3, 2, 0}, {3, 3, 0}};
+// (xt <= yt) of the 4 x 4 tiling are formed; readers take entry
+// (min(x, y), max(x, y)).  For a 4-row slice the MFMA operands of column tile
+// t are the same register for the A and the B side (A(i, k) in lane i + 16k,
+// B(k, j) in lane j + 16k, both G(row k, column 16t + lane % 16)), so a wave
+// loads the 4 tile operands once and issues all 10 products.  Each wave owns
+// every fourth 16-row sub-chunk of the split: it reads the 64 columns of its
+// rows with coalesced loads (lane = row within the sub-chunk), stages them in
+// its own LDS area (no block barrier in the main loop), prefetches the next
+// sub-chunk into registers and accumulates all 10 tiles.  The four waves'
+// tiles are summed in wave order at the end.
+constexpr int kGramTiles = 10;
+__constant__ int kGramTX[kGramTiles] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+__constant__ int kGramTY[kGramTiles] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+
+template <typename T>
+struct GramLd {
+    // LDS row stride of a staged 16 x 64 sub-chunk (elements), chosen so that
+    // the 16 rows written by one load instruction fall into distinct banks
+    static constexpr int value = sizeof(T) == 8 ? kB2 + 2 : kB2 + 4;
+};
 
 template <typename T>
 __global__ __launch_bounds__(256) void block_gram_kernel(BlockArgsT<T> a)
 {
-    __shared__ T Tl[2][kB2 * kLd];
+    constexpr int kLdw = GramLd<T>::value;
+    constexpr int kSub = 16 * kLdw;  // one wave's staging area
+    __shared__ T Xs[4 * kSub];
     __shared__ int cols[kB2];
     if (!bind_problem(a)) return;
     const int k = blockIdx.x, split = blockIdx.y;
@@ -127,74 +145,83 @@ __global__ __launch_bounds__(256) void block_gram_kernel(BlockArgsT<T> a)
     if (threadIdx.x < kB2) cols[threadIdx.x] = a.rho[local_pos(threadIdx.x, IJ.x, IJ.y)];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ntiles = wave < 2 ? 3 : 2;
-    int tx[3], ty[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        tx[q] = kGramTileX[wave][q];
-        ty[q] = kGramTileY[wave][q];
-    }
+    const int lr = lane & 15, lk = lane >> 4;
     const int row_begin = split * a.rows_per_split;
     const int row_end = min(a.ldg, row_begin + a.rows_per_split);
-    const int nchunks = (row_end - row_begin) / 64;
-    typename MF<T>::acc acc[3];
+    const int nsub = (row_end - row_begin) / 16;
+    // load e of a sub-chunk: column 4e + lane / 16, row lane % 16, as 32-bit
+    // byte offsets from the uniform base (r, ldg <= 16448: below 2^32 bytes)
+    const char *__restrict__ G = reinterpret_cast<const char *>(a.G);
+    unsigned off[16];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) acc[q] = MF<T>::zero();
-    // thread's 16 elements of a 64-row chunk: column idx >> 6, row idx & 63
-    const T *src[16];
+    for (int e = 0; e < 16; ++e)
+        off[e] = ((unsigned)cols[4 * e + lk] * (unsigned)a.ldg + (unsigned)(row_begin + lr)) * (unsigned)sizeof(T);
+    auto load = [&](int sub, T *v) {
+        const unsigned rb = (unsigned)(sub * 16) * (unsigned)sizeof(T);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int idx = threadIdx.x + 256 * e;
-        src[e] = a.G + (size_t)cols[idx >> 6] * a.ldg + (idx & 63);
-    }
+        for (int e = 0; e < 16; ++e) v[e] = *reinterpret_cast<const T *>(G + (off[e] + rb));
+    };
+    T *X = Xs + wave * kSub;
+    typename MF<T>::acc acc[kGramTiles];
+#pragma unroll
+    for (int q = 0; q < kGramTiles; ++q) acc[q] = MF<T>::zero();
     T pre[16];
-    if (nchunks > 0) {
+    if (wave < nsub) load(wave, pre);
+    for (int sub = wave; sub < nsub; sub += 4) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) pre[e] = src[e][row_begin];
+        for (int e = 0; e < 16; ++e) X[lr * kLdw + 4 * e + lk] = pre[e];
+        // next sub-chunk (the last one re-reads its own rows, from cache)
+        load(sub + 4 < nsub ? sub + 4 : sub, pre);
+        // the staged rows are read by other lanes of this wave only
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int idx = threadIdx.x + 256 * e;
-            Tl[0][(idx >> 6) * kLd + (idx & 63)] = pre[e];
+        for (int kk = 0; kk < 4; ++kk) {
+            T x[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) x[t] = X[(kk * 4 + lk) * kLdw + t * 16 + lr];
+            acc[0] = MF<T>::mma(x[0], x[0], acc[0]);
+            acc[1] = MF<T>::mma(x[0], x[1], acc[1]);
+            acc[2] = MF<T>::mma(x[0], x[2], acc[2]);
+            acc[3] = MF<T>::mma(x[0], x[3], acc[3]);
+            acc[4] = MF<T>::mma(x[1], x[1], acc[4]);
+            acc[5] = MF<T>::mma(x[1], x[2], acc[5]);
+            acc[6] = MF<T>::mma(x[1], x[3], acc[6]);
+            acc[7] = MF<T>::mma(x[2], x[2], acc[7]);
+            acc[8] = MF<T>::mma(x[2], x[3], acc[8]);
+            acc[9] = MF<T>::mma(x[3], x[3], acc[9]);
         }
+        __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
-    for (int ch = 0; ch < nchunks; ++ch) {
-        const int buf = ch & 1;
-        if (ch + 1 < nchunks) {
-            const int row1 = row_begin + (ch + 1) * 64;
+    // sum over the waves in wave order, five tiles at a time through the
+    // staging area (waves 1..3 deposit, wave 0 adds and stores)
+    T *out = a.partial + ((size_t)k * a.splits + split) * (kB2 * kB2);
+    constexpr int kHalf = kGramTiles / 2;
+    static_assert(3 * kHalf * 256 <= 4 * kSub, "reduction area");
 #pragma unroll
-            for (int e = 0; e < 16; ++e) pre[e] = src[e][row1];
-        }
-#pragma unroll 4
-        for (int kk = 0; kk < 16; ++kk) {
-            const int rr = kk * 4 + (lane >> 4);
+    for (int h = 0; h < 2; ++h) {
+        __syncthreads();
+        if (wave > 0) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                if (q < ntiles) {
-                    const T av = Tl[buf][(tx[q] * 16 + (lane & 15)) * kLd + rr];
-                    const T bv = Tl[buf][(ty[q] * 16 + (lane & 15)) * kLd + rr];
-                    acc[q] = MF<T>::mma(av, bv, acc[q]);
-                }
-            }
-        }
-        if (ch + 1 < nchunks) {
+            for (int j = 0; j < kHalf; ++j)
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int idx = threadIdx.x + 256 * e;
-                Tl[buf ^ 1][(idx >> 6) * kLd + (idx & 63)] = pre[e];
-            }
+                for (int v = 0; v < 4; ++v) Xs[((wave - 1) * kHalf + j) * 256 + v * 64 + lane] = acc[h * kHalf + j][v];
         }
         __syncthreads();
-    }
-    T *out = a.partial + ((size_t)k * a.splits + split) * (kB2 * kB2);
+        if (wave == 0) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        if (q < ntiles) {
+            for (int j = 0; j < kHalf; ++j) {
+                const int q = h * kHalf + j;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int x = tx[q] * 16 + MF<T>::row(lane, v);
-                const int y = ty[q] * 16 + (lane & 15);
-                out[x * kB2 + y] = acc[q][v];
+                for (int v = 0; v < 4; ++v) {
+                    T sum = acc[q][v];
+#pragma unroll
+                    for (int w = 0; w < 3; ++w) sum += Xs[(w * kHalf + j) * 256 + v * 64 + lane];
+                    const int x = kGramTX[q] * 16 + MF<T>::row(lane, v);
+                    const int y = kGramTY[q] * 16 + lr;
+                    out[x * kB2 + y] = sum;
+                }
             }
         }
     }
