@@ -106,6 +106,7 @@ def roofline(infos, names, peaks):
         r = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": ach / HBM_PEAK_GBS}
     r.update({"traffic": None, "kernel": names[q], "avg_launch_us": avg_s * 1e6,
+              "launches_timed": sum(i["kernel_timed"][q] for i in infos), "launches": launches,
               "bytes_per_launch": bpl, "flops_per_launch": fpl,
               "share_of_solve": ms[q] / sum(i["ms_total"] for i in infos)})
     other = {}

@@ -89,10 +89,15 @@ typedef struct {
     long long steps;         /* parallel (outer) steps executed                          */
     long long active_pairs;  /* block pair steps with at least one rotation              */
     double ms_total;         /* device time of the solve (event pair on the stream)      */
-    double kernel_ms[HSVD_NKERNELS];         /* device time per kernel class            */
+    double kernel_ms[HSVD_NKERNELS];         /* device time per kernel class (HIP events);
+                                                block sweeps time the first step of each
+                                                sweep and every 8th step after it and
+                                                count the other steps of that sweep at
+                                                the mean of its timed ones              */
     long long kernel_launches[HSVD_NKERNELS];
     double kernel_bytes[HSVD_NKERNELS];      /* algorithmic bytes (see the design notes) */
     double kernel_flops[HSVD_NKERNELS];      /* algorithmic flops                        */
+    long long kernel_timed[HSVD_NKERNELS];   /* launches that were timed by events      */
 } hsvd_info;
 
 /* Creates a context bound to HIP device `device` and stream `hip_stream`

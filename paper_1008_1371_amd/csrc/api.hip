@@ -267,6 +267,16 @@ hsvd_status hsvd_destroy(hsvd_ctx *ctx)
 
 namespace {
 
+// Per-sweep diagnostics on stderr when HSVD_SWEEP_LOG is set (non-empty, not "0").
+bool sweep_log_enabled()
+{
+    static const bool on = [] {
+        const char *v = getenv("HSVD_SWEEP_LOG");
+        return v && *v && strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
 // Outcome of one sweep, read back from the control block.
 struct SweepResult {
     int code;
@@ -274,15 +284,23 @@ struct SweepResult {
     bool rank;
 };
 
+// Kernel timing of the block sweeps: an event pair around every kernel of
+// every step would itself cost several microseconds per launch, so the
+// first step of a sweep (its own inner kernel) and every kTimeEvery-th step
+// after it are timed, and the other steps of the sweep are counted at the
+// mean of its timed ones.
+constexpr int kTimeEvery = 8;
+
 // Runs block sweeps of storage type T until `done(sweep_result)` says so or
 // max_sweeps is reached.  Kernel times go to kms[kbase + 0..2] (Gram, inner,
-// update).  Returns HSVD_OK, HSVD_E_RANK or HSVD_E_DEVICE; *finished tells
-// whether `done` accepted a sweep.
+// update), the number of timed launches to ktimed.  Returns HSVD_OK,
+// HSVD_E_RANK or HSVD_E_DEVICE; *finished tells whether `done` accepted a
+// sweep.
 template <typename T, typename Done>
 hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, const T *Gcur, int pairs,
                          int steps_per_sweep, int max_sweeps, bool sort, int r, int p, int ldg, long long &gstep,
-                         int kbase, double *kms, long long *klaunch, int &sweeps, long long &steps,
-                         SweepResult &last, bool &finished, Done done)
+                         int kbase, double *kms, long long *klaunch, long long *ktimed, int &sweeps,
+                         long long &steps, SweepResult &last, bool &finished, Done done)
 {
     hipStream_t st = ctx->stream;
     hipEvent_t *ev = ctx->events.data();
@@ -293,13 +311,14 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
             ba.S_in = w.S2 + (gstep & 1) * pairs;
             ba.S_out = w.S2 + ((gstep + 1) & 1) * pairs;
             hipEvent_t *e = ev + 4 + 4 * k;
-            HSVD_TRY(hipEventRecord(e[0], st));
+            const bool tm = k % kTimeEvery == 0;
+            if (tm) HSVD_TRY(hipEventRecord(e[0], st));
             HSVD_TRY(launch_block_gram<T>(st, ba));
-            HSVD_TRY(hipEventRecord(e[1], st));
+            if (tm) HSVD_TRY(hipEventRecord(e[1], st));
             HSVD_TRY(launch_block_inner<T>(st, ba));
-            HSVD_TRY(hipEventRecord(e[2], st));
+            if (tm) HSVD_TRY(hipEventRecord(e[2], st));
             HSVD_TRY(launch_block_update<T>(st, ba));
-            HSVD_TRY(hipEventRecord(e[3], st));
+            if (tm) HSVD_TRY(hipEventRecord(e[3], st));
         }
         for (int q = 0; q < 3; ++q) klaunch[kbase + q] += steps_per_sweep;
         // the kept diagonal: fresh column norms of the updated columns
@@ -309,18 +328,32 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
         HSVD_TRY(launch_sweep_reduce(st, w, pairs));
         HSVD_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
         HSVD_TRY(hipStreamSynchronize(st));
-        for (int k = 0; k < steps_per_sweep; ++k) {
-            hipEvent_t *e = ev + 4 + 4 * k;
+        {
+            double first[3] = {0.0, 0.0, 0.0}, rest[3] = {0.0, 0.0, 0.0};
+            int nrest = 0;
+            for (int k = 0; k < steps_per_sweep; k += kTimeEvery) {
+                hipEvent_t *e = ev + 4 + 4 * k;
+                for (int q = 0; q < 3; ++q) {
+                    float ms = 0.f;
+                    HSVD_TRY(hipEventElapsedTime(&ms, e[q], e[q + 1]));
+                    (k == 0 ? first : rest)[q] += ms;
+                }
+                if (k > 0) ++nrest;
+            }
+            const double scale = nrest > 0 ? (double)(steps_per_sweep - 1) / nrest : 0.0;
             for (int q = 0; q < 3; ++q) {
-                float ms = 0.f;
-                HSVD_TRY(hipEventElapsedTime(&ms, e[q], e[q + 1]));
-                kms[kbase + q] += ms;
+                kms[kbase + q] += first[q] + rest[q] * scale;
+                ktimed[kbase + q] += 1 + nrest;
             }
         }
         ++sweeps;
         last.code = ctx->host_ctl->code;
         last.maxt = ctx->host_ctl->maxt;
         last.rank = ctx->host_ctl->rank != 0;
+        if (sweep_log_enabled())
+            fprintf(stderr, "hsvd sweep %d (%s): max|t| %.3e code %d rotations %llu skips %llu\n", sweeps,
+                    sizeof(T) == 4 ? "fp32" : "fp64", last.maxt, last.code,
+                    (unsigned long long)ctx->host_ctl->rot, (unsigned long long)ctx->host_ctl->skip);
         if (last.rank) return HSVD_E_RANK;
         if (done(last)) {
             finished = true;
@@ -462,6 +495,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
     long long steps = 0;
     double kms[HSVD_NKERNELS] = {0};
     long long klaunch[HSVD_NKERNELS] = {0};
+    long long ktimed[HSVD_NKERNELS] = {0};
     if (ctx->host_ctl->inval) status = HSVD_E_INVAL;
     else if (ctx->host_ctl->rank) status = HSVD_E_RANK;
 
@@ -493,6 +527,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             }
             HSVD_TRY(hipEventRecord(ev[3], st));
             klaunch[HSVD_K_PAIR_STEP] += steps_per_sweep;
+            ktimed[HSVD_K_PAIR_STEP] += steps_per_sweep;
             steps += steps_per_sweep;
             if (prm.sort) HSVD_TRY(launch_sort(st, w.d, w.rho, w.dtmp, w.rtmp, r, p));
             HSVD_TRY(launch_sweep_reduce(st, w, r / 2));
@@ -555,7 +590,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
                 return stop;
             };
             status = block_sweeps<float>(ctx, w, fa, w.G32, pairs, steps_per_sweep, max_sweeps, prm.sort != 0, r,
-                                         p, ldg, gstep, HSVD_K_BLOCK_GRAM32, kms, klaunch, sw32, steps, last,
+                                         p, ldg, gstep, HSVD_K_BLOCK_GRAM32, kms, klaunch, ktimed, sw32, steps, last,
                                          finished, done32);
             sweeps32 = sw32;
             if (status == HSVD_OK) {
@@ -570,6 +605,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
                 HSVD_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
                 kms[HSVD_K_REORTH] += ms;
                 klaunch[HSVD_K_REORTH] += 1;
+                ktimed[HSVD_K_REORTH] += 1;
                 HSVD_TRY(launch_colnorm_pos<double>(st, w.G, ldg, w.rho, w.d, r));
                 if (prm.sort) HSVD_TRY(launch_sort(st, w.d, w.rho, w.dtmp, w.rtmp, r, p));
             }
@@ -599,7 +635,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             ba.tthresh = tthresh;
             auto done64 = [](const SweepResult &sr) { return (sr.code & 2) == 0; };  // eq. (4.2)
             status = block_sweeps<double>(ctx, w, ba, w.G, pairs, steps_per_sweep, max_sweeps, prm.sort != 0, r, p,
-                                          ldg, gstep, HSVD_K_BLOCK_GRAM, kms, klaunch, sweeps, steps, last,
+                                          ldg, gstep, HSVD_K_BLOCK_GRAM, kms, klaunch, ktimed, sweeps, steps, last,
                                           finished, done64);
             code = last.code;
             maxt_last = last.maxt;
@@ -634,6 +670,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
         for (int q = 0; q < HSVD_NKERNELS; ++q) {
             info->kernel_ms[q] = kms[q];
             info->kernel_launches[q] = klaunch[q];
+            info->kernel_timed[q] = ktimed[q];
         }
         if (!block) {
             // a rotated pair reads and writes two columns of G (and of V); a
@@ -840,6 +877,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
 
     double kms[HSVD_NKERNELS] = {0};
     long long klaunch[HSVD_NKERNELS] = {0};
+    long long ktimed[HSVD_NKERNELS] = {0};
     double kbytes[HSVD_NKERNELS] = {0}, kflops[HSVD_NKERNELS] = {0};
     long long tot_rot = 0, tot_skip = 0, tot_act = 0, tot_steps = 0;
     int max_sw = 0;
@@ -1032,6 +1070,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
                         kms[HSVD_K_BLOCK_GRAM + qk] += ms;
                     }
                 }
+                for (int qk = 0; qk < 3; ++qk) ktimed[HSVD_K_BLOCK_GRAM + qk] += steps_per_sweep;
             }
             ++gsweeps;
             if (active == 0) break;
@@ -1093,6 +1132,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         for (int q = 0; q < HSVD_NKERNELS; ++q) {
             info->kernel_ms[q] = kms[q];
             info->kernel_launches[q] = klaunch[q];
+            info->kernel_timed[q] = ktimed[q];
             info->kernel_bytes[q] = kbytes[q];
             info->kernel_flops[q] = kflops[q];
         }

@@ -589,36 +589,76 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
 // (i = output column, j = row) store 16 consecutive rows likewise -- no LDS
 // staging of the data.  W sits in LDS for all strips of the workgroup.
 // ---------------------------------------------------------------------------
-constexpr int kUpdRows = 256;  // rows per workgroup (up to 16 strips of 16 rows, spread over 4 waves)
+// Per storage type: FP32 re-reads W from LDS for every strip and keeps the
+// next strip's rows in flight in registers (low register use, high
+// occupancy); FP64, at twice the registers per operand, holds all 64 W
+// operands in registers across strips instead (measured faster for it).
+template <typename T>
+struct UpdCfg;
+template <>
+struct UpdCfg<float> {
+    static constexpr int rows = 512;       // rows per workgroup
+    static constexpr int ld = kB2 + 16;    // LDS row stride of W: a read's 4 row groups in distinct banks
+    static constexpr bool w_lds = true;    // W re-read from LDS per strip
+    static constexpr int min_blocks = 4;   // workgroups per CU to fit
+};
+template <>
+struct UpdCfg<double> {
+    static constexpr int rows = 256;
+    static constexpr int ld = kB2 + 1;
+    static constexpr bool w_lds = false;
+    static constexpr int min_blocks = 1;
+};
 
 template <typename T>
-__global__ __launch_bounds__(256) void block_update_kernel(BlockArgsT<T> a)
+__global__ __launch_bounds__(256, UpdCfg<T>::min_blocks) void block_update_kernel(BlockArgsT<T> a)
 {
-    __shared__ T Wl[kB2 * kLd];
+    constexpr int kRows = UpdCfg<T>::rows, kUpdLd = UpdCfg<T>::ld;
+    constexpr bool kWLds = UpdCfg<T>::w_lds;
+    __shared__ T Wl[kB2 * kUpdLd];
     __shared__ int cols[kB2];
     const int k = blockIdx.x;
-    const int tiles_g = (a.ldg + kUpdRows - 1) / kUpdRows;
+    const int tiles_g = (a.ldg + kRows - 1) / kRows;
     const int t = blockIdx.y;
     if (t == 0 && blockIdx.z == 0 && threadIdx.x == 0 && a.ordering == HSVD_ORD_MODMOD)
         a.S_out[k] = modmod_next(a.S_in[k], a.nb);
     if (!bind_problem(a)) return;
     if (!a.active[k]) return;  // no rotation in this pair: W = I
     T *__restrict__ M = t < tiles_g ? a.G : a.V;
-    const int row_base = (t < tiles_g ? t : t - tiles_g) * kUpdRows;
-    const int nstrips = min(kUpdRows, a.ldg - row_base) / 16;
+    const int row_base = (t < tiles_g ? t : t - tiles_g) * kRows;
+    const int nstrips = min(kRows, a.ldg - row_base) / 16;
     const int2 IJ = outer_pair(a, k);
     if (threadIdx.x < kB2) cols[threadIdx.x] = a.rho[local_pos(threadIdx.x, IJ.x, IJ.y)];
     const T *Wg = a.W + (size_t)k * (kB2 * kB2);
-    for (int idx = threadIdx.x; idx < kB2 * kB2; idx += 256) Wl[(idx / kB2) * kLd + idx % kB2] = Wg[idx];
+    for (int idx = threadIdx.x; idx < kB2 * kB2; idx += 256) Wl[(idx / kB2) * kUpdLd + idx % kB2] = Wg[idx];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
+    // 32-bit byte offsets from the uniform base (r, ldg <= 16448: below 2^32 bytes).
+    // Loads: B(k = x, j = row) = G(row0 + lr, column x = 4kk + lk).
+    // Stores: D(i = y, j = row), y = 16yt + MF::row(lane, v).
+    char *__restrict__ base = reinterpret_cast<char *>(M);
+    const unsigned row_off = (unsigned)(row_base + lr) * (unsigned)sizeof(T);
+    const unsigned col_bytes = (unsigned)a.ldg * (unsigned)sizeof(T);
+    auto load = [&](int strip, T *bv, const int *cp) {
+        const unsigned rb = (unsigned)(strip * 16) * (unsigned)sizeof(T) + row_off;
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+            bv[kk] = *reinterpret_cast<const T *>(base + ((unsigned)cp[4 * kk + lk] * col_bytes + rb));
+    };
+    T bv[16], nx[16];
+    if (kWLds && wave < nstrips) load(wave, bv, cols);
 #pragma unroll 1
     for (int strip = wave; strip < nstrips; strip += 4) {
-        const int row0 = row_base + strip * 16;
-        T bv[16];
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) bv[kk] = M[(size_t)cols[4 * kk + lk] * a.ldg + row0 + lr];
+        // With kWLds, the opaque zero wz keeps the compiler from hoisting the
+        // column offsets and the 64 W operands into registers across strips.
+        int wz = 0;
+        if (kWLds) asm volatile("" : "+v"(wz));
+        if (kWLds)  // next strip in flight during the products; the last re-reads its own rows
+            load(strip + 4 < nstrips ? strip + 4 : strip, nx, cols + wz);
+        else
+            load(strip, bv, cols);
+        const T *Wp = Wl + wz + lk * kUpdLd + lr;
         typename MF<T>::acc acc[4];
 #pragma unroll
         for (int yt = 0; yt < 4; ++yt) acc[yt] = MF<T>::zero();
@@ -627,15 +667,21 @@ __global__ __launch_bounds__(256) void block_update_kernel(BlockArgsT<T> a)
 #pragma unroll
             for (int yt = 0; yt < 4; ++yt) {
                 // A(i = y, k = x) = W(x, y), x = 4kk + lk, y = 16yt + lr
-                const T aw = Wl[(4 * kk + lk) * kLd + yt * 16 + lr];
+                const T aw = Wp[4 * kk * kUpdLd + yt * 16];
                 acc[yt] = MF<T>::mma(aw, bv[kk], acc[yt]);
             }
-        // result D(i = y, j = row): lane holds y = 16yt + MF::row(lane, v), row = row0 + lr
+        const int *cp = cols + wz;
+        const unsigned rb = (unsigned)(strip * 16) * (unsigned)sizeof(T) + row_off;
 #pragma unroll
         for (int yt = 0; yt < 4; ++yt)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                M[(size_t)cols[yt * 16 + MF<T>::row(lane, v)] * a.ldg + row0 + lr] = acc[yt][v];
+                *reinterpret_cast<T *>(base + ((unsigned)cp[yt * 16 + MF<T>::row(lane, v)] * col_bytes + rb)) =
+                    acc[yt][v];
+        if (kWLds) {
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) bv[kk] = nx[kk];
+        }
     }
 }
 
@@ -732,7 +778,7 @@ hipError_t launch_block_inner(hipStream_t st, const BlockArgsT<T> &a)
 template <typename T>
 hipError_t launch_block_update(hipStream_t st, const BlockArgsT<T> &a)
 {
-    const int tiles = ((a.ldg + kUpdRows - 1) / kUpdRows) * (a.V ? 2 : 1);
+    const int tiles = ((a.ldg + UpdCfg<T>::rows - 1) / UpdCfg<T>::rows) * (a.V ? 2 : 1);
     block_update_kernel<T><<<dim3(a.nb / 2, tiles, a.nprob), 256, 0, st>>>(a);
     return hipGetLastError();
 }

@@ -53,7 +53,8 @@ class hsvd_info(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double * NKERNELS),
                 ("kernel_launches", ctypes.c_longlong * NKERNELS),
                 ("kernel_bytes", ctypes.c_double * NKERNELS),
-                ("kernel_flops", ctypes.c_double * NKERNELS)]
+                ("kernel_flops", ctypes.c_double * NKERNELS),
+                ("kernel_timed", ctypes.c_longlong * NKERNELS)]
 
     def as_dict(self):
         out = {}
