@@ -25,6 +25,43 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a
+# second run, WRITE_SIZE (KiB per dispatch, averaged over all launches of one
+# mixed colscaled4096 solve), each scaled by what the same counter reads for a
+# plain 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  The figures
+# hold only for the kernel source they were taken on: when block_kernels.hip
+# no longer has this SHA-256 the roofline reports traffic as null.
+MEASURED_TRAFFIC = {
+    "workload": "colscaled4096",
+    "mode": "mixed",
+    "source": "paper_1008_1371_amd/csrc/block_kernels.hip",
+    "sha256": "14c06639c0b7c6876053151c404fbfcfb0925bafafba8946bde00100a5d34334",
+    "bytes_per_launch": {
+        "block_update_kernel<float>": (30584.6 * 2.0 + 61553.6) * 1024,
+        "block_gram_kernel<float>": (33002.6 * 2.0 + 10241.8) * 1024,
+        "block_update_kernel<double>": (73934.4 * 2.0 + 143138.0) * 1024,
+        "block_gram_kernel<double>": (66398.0 * 2.0 + 20480.0) * 1024,
+    },
+}
+
+
+def measured_traffic(kernel, workload, mode):
+    """Counter-based HBM bytes per launch of `kernel`, or None when the
+    measurement does not apply (other workload or solve mode, other kernel,
+    changed source)."""
+    import hashlib
+    t = MEASURED_TRAFFIC
+    if workload != t["workload"] or mode != t["mode"] or kernel not in t["bytes_per_launch"]:
+        return None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), t["source"])
+    try:
+        with open(path, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+                return None
+    except OSError:
+        return None
+    return t["bytes_per_launch"][kernel]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -87,7 +124,7 @@ def cpu_baseline(G_np, p, total_steps, block, target_s):
                        f"extrapolated linearly in steps: {est_solve:.0f} s")}
 
 
-def roofline(infos, names, peaks):
+def roofline(infos, names, peaks, workload, mode):
     """Roofline of the kernel class with the most measured time."""
     nk = len(names)
     ms = [sum(i["kernel_ms"][q] for i in infos) for q in range(nk)]
@@ -105,7 +142,7 @@ def roofline(infos, names, peaks):
         ach = bpl / avg_s / 1e9
         r = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": ach / HBM_PEAK_GBS}
-    r.update({"traffic": None, "kernel": names[q], "avg_launch_us": avg_s * 1e6,
+    r.update({"traffic": measured_traffic(names[q], workload, mode), "kernel": names[q], "avg_launch_us": avg_s * 1e6,
               "launches_timed": sum(i["kernel_timed"][q] for i in infos), "launches": launches,
               "bytes_per_launch": bpl, "flops_per_launch": fpl,
               "share_of_solve": ms[q] / sum(i["ms_total"] for i in infos)})
@@ -229,7 +266,7 @@ def main():
                    "tol": 1e-15 * n, "sweeps_fp32": last["sweeps_fp32"], "sweeps_fp64": last["sweeps"],
                    "reorth_iters": last["reorth_iters"], "rotations": last["rotations"],
                    "steps_per_solve": last["steps"]},
-        "roofline": roofline(infos, H.KERNEL_NAMES, peaks),
+        "roofline": roofline(infos, H.KERNEL_NAMES, peaks, args.workload, head),
     }
     if acc is not None:
         line["accuracy"] = acc
@@ -237,7 +274,8 @@ def main():
         if mode == head:
             continue
         line[mode] = {"value": 1000.0 / m_ms, "ms_per_step": m_ms, "sweeps": m_infos[-1]["sweeps"],
-                      "roofline": roofline(m_infos, H.KERNEL_NAMES, peaks), "accuracy": m_acc}
+                      "roofline": roofline(m_infos, H.KERNEL_NAMES, peaks, args.workload, mode),
+                      "accuracy": m_acc}
         line["speedup_vs_" + mode] = m_ms / ms
     if args.batched > 0:
         line["batched"] = batched_line(H, W, ctx, args.batched)
