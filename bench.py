@@ -93,8 +93,10 @@ def accuracy(G, p, R):
     j = torch.ones(n, dtype=torch.float64, device=G.device)
     j[p:] = -1.0
     UtU = U.t() @ U
+    # the stop rule bounds the cosines the solver computes by tol; recomputed
+    # from the returned U they may exceed it by rounding (the tests allow 2 tol)
     out = {"max_offdiag_UtU": (UtU - torch.diag(torch.diagonal(UtU))).abs().max().item(),
-           "tol": 1e-15 * n}
+           "tol": 1e-15 * n, "bound": 2e-15 * n}
     if V is not None:
         VtJV = V.t() @ (V * j[:, None])
         vn = torch.linalg.matrix_norm(V, ord=2).item() ** 2
@@ -109,10 +111,16 @@ def cpu_baseline(G_np, p, total_steps, block, target_s):
     of the same solve; the solve time is extrapolated linearly in steps."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # marginal cost of an outer step (the first step of a sweep is heavier than
+    # the others, and the set-up is paid once)
     t0 = time.perf_counter()
     oracle.hsvd(G_np, p, max_steps=2, nthreads=threads, block=block)
-    probe = time.perf_counter() - t0
-    steps = int(max(2, min(total_steps, 2 * target_s / max(probe, 1e-6))))
+    t2 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.hsvd(G_np, p, max_steps=4, nthreads=threads, block=block)
+    t4 = time.perf_counter() - t0
+    per_step = max((t4 - t2) / 2, t4 / 8, 1e-6)
+    steps = int(max(4, min(total_steps, target_s / per_step)))
     t0 = time.perf_counter()
     R = oracle.hsvd(G_np, p, max_steps=steps, nthreads=threads, block=block)
     dt = time.perf_counter() - t0

@@ -116,12 +116,13 @@ Layout make_layout(int n, int r, int ldg, bool want_v, int pairs, int splits, in
     L.off_nrot = take(sizeof(unsigned int) * slots);
     L.off_nskip = take(sizeof(unsigned int) * slots);
     L.off_nact = take(sizeof(unsigned int) * slots);
+    L.off_ntc = take(sizeof(unsigned int) * slots);
     L.off_maxt = take(sizeof(double) * slots);
     L.off_ctl = take(sizeof(Ctl));
     const size_t bb = (size_t)b2 * b2;
     L.off_P = take(sizeof(double) * (size_t)pairs * splits * bb);
     L.off_W = take(sizeof(double) * (size_t)pairs * bb);
-    L.off_active = take(sizeof(int) * (size_t)pairs);
+    L.off_active = take(sizeof(unsigned long long) * (size_t)pairs);
     L.off_S2 = take(sizeof(int4) * 2 * (size_t)pairs);
     L.mixed = mixed;
     const size_t mat = (size_t)ldg * r;
@@ -150,12 +151,13 @@ Workspace carve(void *base, const Layout &L)
     w.nrot = reinterpret_cast<unsigned int *>(b + L.off_nrot);
     w.nskip = reinterpret_cast<unsigned int *>(b + L.off_nskip);
     w.nact = reinterpret_cast<unsigned int *>(b + L.off_nact);
+    w.ntc = reinterpret_cast<unsigned int *>(b + L.off_ntc);
     w.maxt = reinterpret_cast<double *>(b + L.off_maxt);
     w.ctl = reinterpret_cast<Ctl *>(b + L.off_ctl);
     if (L.pairs > 0) {
         w.P = reinterpret_cast<double *>(b + L.off_P);
         w.W = reinterpret_cast<double *>(b + L.off_W);
-        w.active = reinterpret_cast<int *>(b + L.off_active);
+        w.active = reinterpret_cast<unsigned long long *>(b + L.off_active);
         w.S2 = reinterpret_cast<int4 *>(b + L.off_S2);
     }
     if (L.mixed) {
@@ -491,6 +493,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
 
     hsvd_status status = HSVD_OK;
     int sweeps = 0, sweeps32 = 0, code = 0, ns_iters = 0;
+    unsigned long long tcol32 = 0;  // touched columns of the FP32 phase (cumulative counter at its end)
     double maxt_last = 0.0, ns_resid = 0.0;
     long long steps = 0;
     double kms[HSVD_NKERNELS] = {0};
@@ -573,6 +576,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             fa.nrot = w.nrot;
             fa.nskip = w.nskip;
             fa.nact = w.nact;
+            fa.ntc = w.ntc;
             fa.maxt = w.maxt;
             fa.ctl = w.ctl;
             // the FP32 Gram resolves cosines down to about sqrt(r) FP32 epsilons
@@ -593,6 +597,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
                                          p, ldg, gstep, HSVD_K_BLOCK_GRAM32, kms, klaunch, ktimed, sw32, steps, last,
                                          finished, done32);
             sweeps32 = sw32;
+            tcol32 = ctx->host_ctl->tcol;
             if (status == HSVD_OK) {
                 // back to FP64: X = J-orthogonalised V32, G1 = G X, V0 = X
                 HSVD_TRY(hipEventRecord(ev[2], st));
@@ -629,6 +634,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             ba.nrot = w.nrot;
             ba.nskip = w.nskip;
             ba.nact = w.nact;
+            ba.ntc = w.ntc;
             ba.maxt = w.maxt;
             ba.ctl = w.ctl;
             ba.tol = tol;
@@ -681,25 +687,25 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             info->kernel_flops[HSVD_K_PAIR_STEP] = rot * (12.0 + 6.0 * (vmul - 1.0)) * rows + skp * 2.0 * rows;
         } else {
             // per block pair and step: the Gram reads 2b columns and does a full
-            // (2b)^2 x rows product; an active pair's update reads and writes the
-            // 2b columns of G (and of V) with (2b)^2 x rows multiply-adds each.
-            // Active pair steps are not split by precision: the update figures
-            // use the share of steps each precision ran.
+            // (2b)^2 x rows product; the update must read and write only the
+            // columns of G (and of V) that a rotation touched, each the product
+            // of 2b columns with a column of W (2b x rows multiply-adds).  The
+            // FP32 phase of the mixed path always carries V.
             const double b2 = 2.0 * b;
-            const double act = (double)info->active_pairs;
+            const double tc_all = (double)ctx->host_ctl->tcol;
             const double st64 = (double)klaunch[HSVD_K_BLOCK_GRAM], st32 = (double)klaunch[HSVD_K_BLOCK_GRAM32];
-            const double frac64 = (st64 + st32) > 0 ? st64 / (st64 + st32) : 1.0;
             for (int prec = 0; prec < 2; ++prec) {
                 const int kb = prec == 0 ? HSVD_K_BLOCK_GRAM : HSVD_K_BLOCK_GRAM32;
                 const double esz = prec == 0 ? 8.0 : 4.0;
                 const double visits = (prec == 0 ? st64 : st32) * pairs;
-                const double acts = act * (prec == 0 ? frac64 : 1.0 - frac64);
+                const double tcols = prec == 0 ? tc_all - (double)tcol32 : (double)tcol32;
+                const double vm = prec == 0 ? vmul : 2.0;
                 info->kernel_bytes[kb] = visits * esz * b2 * rows;
                 info->kernel_flops[kb] = visits * 2.0 * b2 * b2 * rows;
                 info->kernel_bytes[kb + 1] = visits * (double)(splits * esz + 2 * esz) * b2 * b2;
                 info->kernel_flops[kb + 1] = 0.0;
-                info->kernel_bytes[kb + 2] = acts * 2.0 * esz * b2 * rows * vmul;
-                info->kernel_flops[kb + 2] = acts * 2.0 * b2 * b2 * rows * vmul;
+                info->kernel_bytes[kb + 2] = tcols * 2.0 * esz * rows * vm;
+                info->kernel_flops[kb + 2] = tcols * 2.0 * b2 * rows * vm;
             }
             if (mixed) {
                 const double rr = (double)r;
@@ -906,12 +912,13 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         const size_t o_nr = take_bytes(o, sizeof(unsigned) * pairs * K);
         const size_t o_ns = take_bytes(o, sizeof(unsigned) * pairs * K);
         const size_t o_na = take_bytes(o, sizeof(unsigned) * pairs * K);
+        const size_t o_ntc = take_bytes(o, sizeof(unsigned) * pairs * K);
         const size_t o_mt = take_bytes(o, sizeof(double) * pairs * K);
         const size_t o_ctl = take_bytes(o, sizeof(Ctl) * K);
         const size_t o_S2 = take_bytes(o, sizeof(int4) * 2 * pairs);
         const size_t o_P = take_bytes(o, sizeof(double) * pairs * bb * K);
         const size_t o_W = take_bytes(o, sizeof(double) * pairs * bb * K);
-        const size_t o_act = take_bytes(o, sizeof(int) * pairs * K);
+        const size_t o_act = take_bytes(o, sizeof(unsigned long long) * pairs * K);
         s = ensure_ws(ctx, o);
         if (s != HSVD_OK) return s;
         char *base = static_cast<char *>(ctx->ws);
@@ -964,6 +971,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         g.nrot = reinterpret_cast<unsigned *>(base + o_nr);
         g.nskip = reinterpret_cast<unsigned *>(base + o_ns);
         g.nact = reinterpret_cast<unsigned *>(base + o_na);
+        g.ntc = reinterpret_cast<unsigned *>(base + o_ntc);
         g.maxt = reinterpret_cast<double *>(base + o_mt);
         g.ctl = reinterpret_cast<Ctl *>(base + o_ctl);
         int4 *S2 = reinterpret_cast<int4 *>(base + o_S2);
@@ -985,11 +993,12 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         ba.splits = 1;
         ba.rows_per_split = ldg;
         ba.W = reinterpret_cast<double *>(base + o_W);
-        ba.active = reinterpret_cast<int *>(base + o_act);
+        ba.active = reinterpret_cast<unsigned long long *>(base + o_act);
         ba.C = g.C;
         ba.nrot = g.nrot;
         ba.nskip = g.nskip;
         ba.nact = g.nact;
+        ba.ntc = g.ntc;
         ba.maxt = g.maxt;
         ba.ctl = g.ctl;
         ba.tol = 0.0;
@@ -1088,7 +1097,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         HSVD_TRY(hipMemcpyAsync(hsw.data(), g.sweeps, sizeof(int) * K, hipMemcpyDeviceToHost, st));
         HSVD_TRY(hipMemcpyAsync(hctl.data(), g.ctl, sizeof(Ctl) * K, hipMemcpyDeviceToHost, st));
         HSVD_TRY(hipStreamSynchronize(st));
-        long long act = 0;
+        long long act = 0, tcol = 0;
         for (int z = 0; z < K; ++z) {
             all_status[ids[z]] = hs[z];
             all_sweeps[ids[z]] = hsw[z];
@@ -1096,6 +1105,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
             tot_rot += (long long)hctl[z].rot;
             tot_skip += (long long)hctl[z].skip;
             act += (long long)hctl[z].act;
+            tcol += (long long)hctl[z].tcol;
         }
         tot_act += act;
         // algorithmic work of the group (see hsvd_solve): Gram of every pair
@@ -1106,8 +1116,8 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         kbytes[HSVD_K_BLOCK_GRAM] += (double)visits * 8.0 * b2 * rows;
         kflops[HSVD_K_BLOCK_GRAM] += (double)visits * 2.0 * b2 * b2 * rows;
         kbytes[HSVD_K_BLOCK_INNER] += (double)visits * 3.0 * 8.0 * b2 * b2;
-        kbytes[HSVD_K_BLOCK_UPDATE] += (double)act * 16.0 * b2 * rows * vmul;
-        kflops[HSVD_K_BLOCK_UPDATE] += (double)act * 2.0 * b2 * b2 * rows * vmul;
+        kbytes[HSVD_K_BLOCK_UPDATE] += (double)tcol * 16.0 * rows * vmul;
+        kflops[HSVD_K_BLOCK_UPDATE] += (double)tcol * 2.0 * b2 * rows * vmul;
         (void)gsweeps;
     }
     HSVD_TRY(hipEventRecord(ev[1], st));

@@ -62,6 +62,7 @@ __global__ __launch_bounds__(256) void batch_colnorm_kernel(BatchGroup g, int in
                 g.nrot[k] = 0;
                 g.nskip[k] = 0;
                 g.nact[k] = 0;
+                g.ntc[k] = 0;
                 g.maxt[k] = 0.0;
             }
         }
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(64) void batch_reduce_decide_kernel(BatchGroup g)
     const int z = blockIdx.x;
     if (g.done[z]) return;
     int code = 0;
-    unsigned long long rot = 0, skp = 0, act = 0;
+    unsigned long long rot = 0, skp = 0, act = 0, tc = 0;
     double mx = 0.0;
     for (int q = threadIdx.x; q < g.pairs; q += 64) {
         const size_t k = (size_t)z * g.pairs + q;
@@ -134,11 +135,13 @@ __global__ __launch_bounds__(64) void batch_reduce_decide_kernel(BatchGroup g)
         rot += g.nrot[k];
         skp += g.nskip[k];
         act += g.nact[k];
+        tc += g.ntc[k];
         mx = fmax(mx, g.maxt[k]);
         g.C[k] = 0;
         g.nrot[k] = 0;
         g.nskip[k] = 0;
         g.nact[k] = 0;
+        g.ntc[k] = 0;
         g.maxt[k] = 0.0;
     }
 #pragma unroll
@@ -147,6 +150,7 @@ __global__ __launch_bounds__(64) void batch_reduce_decide_kernel(BatchGroup g)
         rot += __shfl_xor(rot, m, 64);
         skp += __shfl_xor(skp, m, 64);
         act += __shfl_xor(act, m, 64);
+        tc += __shfl_xor(tc, m, 64);
         mx = fmax(mx, __shfl_xor(mx, m, 64));
     }
     if (threadIdx.x == 0) {
@@ -155,6 +159,7 @@ __global__ __launch_bounds__(64) void batch_reduce_decide_kernel(BatchGroup g)
         ctl->rot += rot;
         ctl->skip += skp;
         ctl->act += act;
+        ctl->tcol += tc;
         ctl->maxt = mx;
         const int sw = g.sweeps[z] + 1;
         g.sweeps[z] = sw;
@@ -212,6 +217,7 @@ __global__ void batch_zero_ctl_kernel(Ctl *ctl, int nprob, int *active_count)
     ctl[z].rot = 0;
     ctl[z].skip = 0;
     ctl[z].act = 0;
+    ctl[z].tcol = 0;
     ctl[z].maxt = 0.0;
     ctl[z].nsres = 0.0;
 }

@@ -84,6 +84,7 @@ __device__ __forceinline__ bool bind_problem(BlockArgsT<T> &a)
     a.nrot += (size_t)z * pairs;
     a.nskip += (size_t)z * pairs;
     a.nact += (size_t)z * pairs;
+    a.ntc += (size_t)z * pairs;
     a.maxt += (size_t)z * pairs;
     a.ctl += z;
     if (a.pvec) a.p = a.pvec[z];
@@ -238,6 +239,7 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
     __shared__ double pt[kB], pc[kB], pht[kB];
     __shared__ int px[kB], py[kB], prot[kB];
     __shared__ int s_code, s_rot, s_skip, s_any;
+    __shared__ unsigned long long s_mask;  // local columns touched by a rotation
     __shared__ double s_maxt[kB];
     if (!bind_problem(a)) return;
     const int k = blockIdx.x;
@@ -264,6 +266,7 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
         s_rot = 0;
         s_skip = 0;
         s_any = 0;
+        s_mask = 0ull;
     }
     __syncthreads();
 
@@ -271,6 +274,7 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
     const int inner_steps = first ? kB2 - 1 : kB;
     int code = 0, nrot = 0, nskip = 0, rank = 0;
     double maxt = 0.0;
+    unsigned long long tmask = 0ull;
     for (int u = 0; u < inner_steps; ++u) {
         if (threadIdx.x < kB) {
             const int q = threadIdx.x;
@@ -297,6 +301,7 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
                 }
             }
             if (!rot) pht[q] = 0.0;
+            if (rot) tmask |= (1ull << x) | (1ull << y);
             pt[q] = t;
             pc[q] = c;
             px[q] = x;
@@ -359,6 +364,7 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
         if (nrot) atomicAdd(&s_rot, nrot);
         if (nskip) atomicAdd(&s_skip, nskip);
         if (rank) atomicOr(&a.ctl->rank, 1);
+        if (tmask) atomicOr(&s_mask, tmask);
         s_maxt[threadIdx.x] = maxt;
     }
     T *Wg = a.W + (size_t)k * (kB2 * kB2);
@@ -375,7 +381,8 @@ __global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
         a.nrot[k] += (unsigned)s_rot;
         a.nskip[k] += (unsigned)s_skip;
         a.nact[k] += s_rot > 0 ? 1u : 0u;
-        a.active[k] = s_rot > 0 ? 1 : 0;
+        a.ntc[k] += (unsigned)__popcll(s_mask);
+        a.active[k] = s_mask;
     }
 }
 
@@ -469,6 +476,7 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
     double pll = LL, plr = LR, prr = RR;
     int code = 0, nrot = 0, nskip = 0, rank = 0;
     double maxt = 0.0;
+    unsigned long long tmask = 0ull;  // local columns touched by a rotation (first wave)
     const double tol2 = a.tol * a.tol;
     if (tid < 64) __builtin_amdgcn_s_setprio(2);
     __syncthreads();
@@ -499,6 +507,7 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
                 code |= rotation_code(t, a.tthresh);
                 maxt = fmax(maxt, fabs(t));
                 h = hyp < 0 ? -t : t;
+                tmask |= (1ull << s) | (1ull << (kB + ((s + u) & 31)));
             }
             prm[pb][s] = make_double4(t, c, h, rot ? 1.0 : 0.0);
         }
@@ -560,6 +569,7 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
     if (tid < 64) {
         // counters of the b slots, reduced within the first wave
         unsigned rot_sum = (unsigned)nrot, skip_sum = (unsigned)nskip;
+        unsigned mlo = (unsigned)tmask, mhi = (unsigned)(tmask >> 32);
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) {
             code |= __shfl_xor(code, m, 64);
@@ -567,15 +577,19 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
             rot_sum += __shfl_xor(rot_sum, m, 64);
             skip_sum += __shfl_xor(skip_sum, m, 64);
             maxt = fmax(maxt, __shfl_xor(maxt, m, 64));
+            mlo |= __shfl_xor(mlo, m, 64);
+            mhi |= __shfl_xor(mhi, m, 64);
         }
         if (tid == 0) {
+            const unsigned long long mask = ((unsigned long long)mhi << 32) | mlo;
             if (rank) atomicOr(&a.ctl->rank, 1);
             a.maxt[k] = fmax(a.maxt[k], maxt);
             a.C[k] |= code;
             a.nrot[k] += rot_sum;
             a.nskip[k] += skip_sum;
             a.nact[k] += rot_sum > 0 ? 1u : 0u;
-            a.active[k] = rot_sum > 0 ? 1 : 0;
+            a.ntc[k] += (unsigned)__popcll(mask);
+            a.active[k] = mask;
         }
     }
 }
@@ -610,6 +624,56 @@ struct UpdCfg<double> {
     static constexpr int min_blocks = 1;
 };
 
+// Compact update of a block pair whose rotations touched only m <= NC of its
+// 2b local columns (list tl, physical columns cols): the other columns of W
+// are unit columns and every touched column of W is zero outside the touched
+// rows (rotations only combine touched columns), so [G_T | V_T] <- [G_T | V_T]
+// W_TT is the whole update.  Same MFMA formulation as the full update with NC
+// columns, W_TT zero-padded to NC x NC; only the m touched columns are read
+// and written.
+template <typename T, int NC>
+__device__ __forceinline__ void update_compact(const BlockArgsT<T> &a, int k, T *__restrict__ M, int row_base,
+                                               int nstrips, T *Wl, const int *cols, const int *tl, int m)
+{
+    const T *Wg = a.W + (size_t)k * (kB2 * kB2);
+    for (int idx = threadIdx.x; idx < NC * NC; idx += 256) {
+        const int i = idx / NC, j = idx % NC;
+        Wl[idx] = (i < m && j < m) ? Wg[tl[i] * kB2 + tl[j]] : T(0);
+    }
+    __syncthreads();
+    constexpr int KK = NC / 4, YT = NC / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    char *__restrict__ base = reinterpret_cast<char *>(M);
+    const unsigned row_off = (unsigned)(row_base + lr) * (unsigned)sizeof(T);
+    const unsigned col_bytes = (unsigned)a.ldg * (unsigned)sizeof(T);
+#pragma unroll 1
+    for (int strip = wave; strip < nstrips; strip += 4) {
+        const unsigned rb = (unsigned)(strip * 16) * (unsigned)sizeof(T) + row_off;
+        T bv[KK];
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            const int x = 4 * kk + lk;
+            bv[kk] = x < m ? *reinterpret_cast<const T *>(base + ((unsigned)cols[x] * col_bytes + rb)) : T(0);
+        }
+        typename MF<T>::acc acc[YT];
+#pragma unroll
+        for (int yt = 0; yt < YT; ++yt) acc[yt] = MF<T>::zero();
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+            for (int yt = 0; yt < YT; ++yt)
+                acc[yt] = MF<T>::mma(Wl[(4 * kk + lk) * NC + yt * 16 + lr], bv[kk], acc[yt]);
+#pragma unroll
+        for (int yt = 0; yt < YT; ++yt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int y = yt * 16 + MF<T>::row(lane, v);
+                if (y < m) *reinterpret_cast<T *>(base + ((unsigned)cols[y] * col_bytes + rb)) = acc[yt][v];
+            }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256, UpdCfg<T>::min_blocks) void block_update_kernel(BlockArgsT<T> a)
 {
@@ -617,17 +681,34 @@ __global__ __launch_bounds__(256, UpdCfg<T>::min_blocks) void block_update_kerne
     constexpr bool kWLds = UpdCfg<T>::w_lds;
     __shared__ T Wl[kB2 * kUpdLd];
     __shared__ int cols[kB2];
+    __shared__ int tl[kB2];
     const int k = blockIdx.x;
     const int tiles_g = (a.ldg + kRows - 1) / kRows;
     const int t = blockIdx.y;
     if (t == 0 && blockIdx.z == 0 && threadIdx.x == 0 && a.ordering == HSVD_ORD_MODMOD)
         a.S_out[k] = modmod_next(a.S_in[k], a.nb);
     if (!bind_problem(a)) return;
-    if (!a.active[k]) return;  // no rotation in this pair: W = I
+    const unsigned long long mask = a.active[k];
+    if (!mask) return;  // no rotation in this pair: W = I
     T *__restrict__ M = t < tiles_g ? a.G : a.V;
     const int row_base = (t < tiles_g ? t : t - tiles_g) * kRows;
     const int nstrips = min(kRows, a.ldg - row_base) / 16;
     const int2 IJ = outer_pair(a, k);
+    const int m = __popcll(mask);
+    if (m <= 32) {
+        // compact list of the touched local columns, in increasing order
+        if (threadIdx.x < kB2 && ((mask >> threadIdx.x) & 1ull)) {
+            const int i = __popcll(mask & ((1ull << threadIdx.x) - 1ull));
+            tl[i] = threadIdx.x;
+            cols[i] = a.rho[local_pos(threadIdx.x, IJ.x, IJ.y)];
+        }
+        __syncthreads();
+        if (m <= 16)
+            update_compact<T, 16>(a, k, M, row_base, nstrips, Wl, cols, tl, m);
+        else
+            update_compact<T, 32>(a, k, M, row_base, nstrips, Wl, cols, tl, m);
+        return;
+    }
     if (threadIdx.x < kB2) cols[threadIdx.x] = a.rho[local_pos(threadIdx.x, IJ.x, IJ.y)];
     const T *Wg = a.W + (size_t)k * (kB2 * kB2);
     for (int idx = threadIdx.x; idx < kB2 * kB2; idx += 256) Wl[(idx / kB2) * kUpdLd + idx % kB2] = Wg[idx];

@@ -25,6 +25,7 @@ struct Ctl {
     unsigned long long rot;    // rotations, cumulative
     unsigned long long skip;   // skipped pair visits, cumulative
     unsigned long long act;    // block pair steps with a rotation, cumulative
+    unsigned long long tcol;   // columns touched by a rotation, summed over block pair steps, cumulative
     double maxt;               // largest |t| of the sweep just reduced
     double nsres;              // Newton-Schulz residual max |J X^T J X - I| (mixed path)
 };
@@ -41,12 +42,13 @@ struct Workspace {
     unsigned int *nrot = nullptr;   // r/2: per-slot rotations in the current sweep
     unsigned int *nskip = nullptr;  // r/2: per-slot skips in the current sweep
     unsigned int *nact = nullptr;   // r/2: per-slot steps with at least one rotation (block path)
+    unsigned int *ntc = nullptr;    // r/2: per-slot columns touched by rotations, summed over steps (block path)
     double *maxt = nullptr;         // r/2: per-slot largest |t| of the current sweep
     Ctl *ctl = nullptr;
     // block path
     double *P = nullptr;      // pairs x splits x (2b)^2 partial Gram matrices
     double *W = nullptr;      // pairs x (2b)^2 accumulated inner transformations
-    int *active = nullptr;    // pairs: 1 when the pair's W is not the identity
+    unsigned long long *active = nullptr;  // pairs: mask of the 2b local columns W changes (0: W = I)
     int4 *S2 = nullptr;       // 2 x pairs: outer stepper state, double-buffered across steps
     // mixed path
     float *G32 = nullptr, *V32 = nullptr, *P32 = nullptr, *W32 = nullptr;
@@ -57,7 +59,7 @@ struct Layout {
     int n = 0, r = 0, ldg = 0, pairs = 0, splits = 0, b2 = 0;
     size_t bytes = 0;
     size_t off_G, off_V, off_d, off_rho, off_dtmp, off_rtmp, off_S, off_C, off_nrot, off_nskip,
-        off_nact, off_maxt, off_ctl, off_P, off_W, off_active, off_S2, off_G32, off_V32, off_P32, off_W32,
+        off_nact, off_ntc, off_maxt, off_ctl, off_P, off_W, off_active, off_S2, off_G32, off_V32, off_P32, off_W32,
         off_T1, off_T2;
     bool mixed = false;
 };
@@ -318,9 +320,9 @@ struct BlockArgsT {
     T *partial;
     int splits, rows_per_split;
     T *W;
-    int *active;
+    unsigned long long *active;  // per pair: mask of the 2b local columns W changes (0: W = I)
     int *C;
-    unsigned int *nrot, *nskip, *nact;
+    unsigned int *nrot, *nskip, *nact, *ntc;
     double *maxt;            // per slot: largest |t| of the sweep
     Ctl *ctl;
     double tol, tthresh;
@@ -376,7 +378,7 @@ struct BatchGroup {
     double *G, *V, *d, *dtmp;
     int *rho, *rtmp;
     int *C;
-    unsigned int *nrot, *nskip, *nact;
+    unsigned int *nrot, *nskip, *nact, *ntc;
     double *maxt;
     Ctl *ctl;
 };

@@ -40,6 +40,7 @@ __global__ __launch_bounds__(WG) void precompute_kernel(const double *__restrict
                                                         unsigned int *__restrict__ nrot,
                                                         unsigned int *__restrict__ nskip,
                                                         unsigned int *__restrict__ nact,
+                                                        unsigned int *__restrict__ ntc,
                                                         double *__restrict__ maxt, Ctl *ctl)
 {
     __shared__ double sh[WG / 64];
@@ -62,6 +63,7 @@ __global__ __launch_bounds__(WG) void precompute_kernel(const double *__restrict
             nrot[c] = 0;
             nskip[c] = 0;
             nact[c] = 0;
+            ntc[c] = 0;
             maxt[c] = 0.0;
         }
     }
@@ -241,25 +243,28 @@ __global__ __launch_bounds__(1024) void sweep_reduce_kernel(int *__restrict__ C,
                                                             unsigned int *__restrict__ nrot,
                                                             unsigned int *__restrict__ nskip,
                                                             unsigned int *__restrict__ nact,
+                                                            unsigned int *__restrict__ ntc,
                                                             double *__restrict__ maxt,
                                                             int slots, Ctl *ctl)
 {
     __shared__ int scode[16];
-    __shared__ unsigned long long srot[16], sskip[16], sact[16];
+    __shared__ unsigned long long srot[16], sskip[16], sact[16], stc[16];
     __shared__ double smax[16];
     int code = 0;
-    unsigned long long rot = 0, skp = 0, act = 0;
+    unsigned long long rot = 0, skp = 0, act = 0, tc = 0;
     double mx = 0.0;
     for (int k = threadIdx.x; k < slots; k += 1024) {
         code |= C[k];
         rot += nrot[k];
         skp += nskip[k];
         act += nact[k];
+        tc += ntc[k];
         mx = fmax(mx, maxt[k]);
         C[k] = 0;
         nrot[k] = 0;
         nskip[k] = 0;
         nact[k] = 0;
+        ntc[k] = 0;
         maxt[k] = 0.0;
     }
 #pragma unroll
@@ -268,6 +273,7 @@ __global__ __launch_bounds__(1024) void sweep_reduce_kernel(int *__restrict__ C,
         rot += __shfl_xor(rot, m, 64);
         skp += __shfl_xor(skp, m, 64);
         act += __shfl_xor(act, m, 64);
+        tc += __shfl_xor(tc, m, 64);
         mx = fmax(mx, __shfl_xor(mx, m, 64));
     }
     const int w = threadIdx.x >> 6;
@@ -276,24 +282,27 @@ __global__ __launch_bounds__(1024) void sweep_reduce_kernel(int *__restrict__ C,
         srot[w] = rot;
         sskip[w] = skp;
         sact[w] = act;
+        stc[w] = tc;
         smax[w] = mx;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int cc = 0;
-        unsigned long long rr = 0, ss = 0, aa = 0;
+        unsigned long long rr = 0, ss = 0, aa = 0, tt = 0;
         double mm = 0.0;
         for (int q = 0; q < 16; ++q) {
             cc |= scode[q];
             rr += srot[q];
             ss += sskip[q];
             aa += sact[q];
+            tt += stc[q];
             mm = fmax(mm, smax[q]);
         }
         ctl->code = cc;
         ctl->rot += rr;
         ctl->skip += ss;
         ctl->act += aa;
+        ctl->tcol += tt;
         ctl->maxt = mm;
     }
 }
@@ -308,6 +317,7 @@ __global__ void zero_ctl_kernel(Ctl *ctl)
         ctl->rot = 0;
         ctl->skip = 0;
         ctl->act = 0;
+        ctl->tcol = 0;
         ctl->maxt = 0.0;
         ctl->nsres = 0.0;
     }
@@ -437,7 +447,7 @@ hipError_t launch_setup(hipStream_t st, const double *G, int lda, int n, const W
 hipError_t launch_precompute(hipStream_t st, const Workspace &w, int r, int ldg)
 {
     precompute_kernel<256><<<r, 256, 0, st>>>(w.G, ldg, r, w.d, w.rho, w.S, w.C, w.nrot, w.nskip,
-                                              w.nact, w.maxt, w.ctl);
+                                              w.nact, w.ntc, w.maxt, w.ctl);
     return hipGetLastError();
 }
 
@@ -474,7 +484,7 @@ hipError_t launch_sort(hipStream_t st, double *d, int *rho, double *dtmp, int *r
 
 hipError_t launch_sweep_reduce(hipStream_t st, const Workspace &w, int slots)
 {
-    sweep_reduce_kernel<<<1, 1024, 0, st>>>(w.C, w.nrot, w.nskip, w.nact, w.maxt, slots, w.ctl);
+    sweep_reduce_kernel<<<1, 1024, 0, st>>>(w.C, w.nrot, w.nskip, w.nact, w.ntc, w.maxt, slots, w.ctl);
     return hipGetLastError();
 }
 
