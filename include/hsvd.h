@@ -58,6 +58,14 @@ typedef struct {
     double t_thresh; /* T of eq. (4.2); <= 0: sqrt(tol) / 2 (Sec. 2)                     */
     int graph;       /* hsvd_solve_batched: 1 = capture one sweep of a group as a HIP
                         graph and replay it (no per-kernel timing in hsvd_info)        */
+    int inner_sweeps; /* block path.  0: block-oriented method (Sec. 5) -- each outer step
+                        annihilates the pivot block's off-diagonal entries once (all pairs
+                        of the 2b columns in the first outer step of a sweep, the cross
+                        pairs in the others).  k in [1, 100]: full-block method (Sec. 6)
+                        -- each outer step diagonalises the pivot block by sweeps of the
+                        pointwise method over its 2b columns until one rotates nothing, at
+                        most k.  k > 0 makes HSVD_AUTO take the block path; the pairwise
+                        path rejects k > 0 with HSVD_E_INVAL                           */
 } hsvd_params;
 
 /* Kernel classes timed in hsvd_info (index into the kernel_* arrays). */

@@ -39,12 +39,14 @@ class _Params(ctypes.Structure):
     _fields_ = [("ordering", ctypes.c_int), ("sort", ctypes.c_int), ("want_v", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("tol", ctypes.c_double),
                 ("tthresh", ctypes.c_double), ("block", ctypes.c_int),
-                ("max_steps", ctypes.c_long), ("nthreads", ctypes.c_int)]
+                ("max_steps", ctypes.c_long), ("nthreads", ctypes.c_int),
+                ("inner_sweeps", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int), ("code", ctypes.c_int), ("rotations", ctypes.c_long),
-                ("skips", ctypes.c_long), ("steps", ctypes.c_long), ("r", ctypes.c_int)]
+                ("skips", ctypes.c_long), ("steps", ctypes.c_long), ("r", ctypes.c_int),
+                ("inner", ctypes.c_long)]
 
 
 _lib = None
@@ -104,7 +106,7 @@ def default_tol(n: int) -> float:
 
 
 def hsvd(G, p, *, ordering="modmod", sort=True, want_v=True, max_sweeps=100, tol=None,
-         tthresh=None, block=0, max_steps=0, nthreads=0):
+         tthresh=None, block=0, max_steps=0, nthreads=0, inner_sweeps=0):
     """Run the oracle.  G: (n, n) float64 array (any order).  Returns a dict
     with status, sigma, U, V, lam, perm and the iteration counters."""
     G = np.asarray(G, dtype=np.float64)
@@ -115,7 +117,7 @@ def hsvd(G, p, *, ordering="modmod", sort=True, want_v=True, max_sweeps=100, tol
     tthresh = (np.sqrt(tol) / 2.0) if tthresh is None else float(tthresh)
     prm = _Params(MODMOD if ordering == "modmod" else ROUNDROBIN, int(bool(sort)),
                   int(bool(want_v)), int(max_sweeps), tol, tthresh, int(block),
-                  int(max_steps), int(nthreads))
+                  int(max_steps), int(nthreads), int(inner_sweeps))
     sigma = np.zeros(n)
     U = np.zeros((n, n), order="F")
     V = np.zeros((n, n), order="F") if want_v else None
@@ -127,7 +129,7 @@ def hsvd(G, p, *, ordering="modmod", sort=True, want_v=True, max_sweeps=100, tol
                         ctypes.byref(info))
     return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, perm=perm, sweeps=info.sweeps,
                 code=info.code, rotations=info.rotations, skips=info.skips, steps=info.steps,
-                r=info.r, tol=tol, tthresh=tthresh)
+                r=info.r, inner=info.inner, tol=tol, tthresh=tthresh)
 
 
 def rotation(aii, ajj, aij, hyp):

@@ -404,7 +404,7 @@ int orc_hsvd(int n, int p, const double *G, int ldg, const orc_params *prm,
 
     orc_state st = {r, p, Gw, Vw, d, rho, prm->tol, prm->tthresh};
     int sweeps = 0, code = 0;
-    long rot = 0, skp = 0, steps = 0;
+    long rot = 0, skp = 0, steps = 0, inner = 0;
     int converged = 0, stopped = 0;
 
     if (status == ORC_OK) {
@@ -426,6 +426,29 @@ int orc_hsvd(int n, int p, const double *G, int ldg, const orc_params *prm,
                         scode |= acc.code; srank |= acc.rank;
                         srot += acc.rot; sskp += acc.skip;
                     }
+                } else if (prm->inner_sweeps > 0) {
+                    /* full-block: every pair of the 2b columns by the circle
+                       method, repeated until an inner sweep rotates nothing */
+                    int cnt = orc_block_step_pairs(r, b, outer, 0, pairs);
+                    int per = cnt / (outer_r / 2);
+                    int nbp = outer_r / 2;
+                    long sinner = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(|:scode, srank) reduction(+:srot, sskp, sinner)
+                    for (int k = 0; k < nbp; ++k) {
+                        orc_acc acc = {0, 0, 0, 0};
+                        for (int it = 0; it < prm->inner_sweeps; ++it) {
+                            long before = acc.rot;
+                            for (int q = 0; q < per; ++q) {
+                                int *pq = pairs + 2 * ((size_t)k * per + q);
+                                pair_rotate(&st, pq[0], pq[1], &acc);
+                            }
+                            ++sinner;
+                            if (acc.rot == before) break;
+                        }
+                        scode |= acc.code; srank |= acc.rank;
+                        srot += acc.rot; sskp += acc.skip;
+                    }
+                    inner += sinner;
                 } else {
                     int cnt = orc_block_step_pairs(r, b, outer, s, pairs);
                     int per = cnt / (outer_r / 2);
@@ -481,6 +504,7 @@ int orc_hsvd(int n, int p, const double *G, int ldg, const orc_params *prm,
         info->skips = skp;
         info->steps = steps;
         info->r = r;
+        info->inner = inner;
     }
     free(Gw); free(Vw); free(d); free(rho); free(mm_state); free(outer); free(pairs);
     return status;

@@ -41,6 +41,11 @@ typedef struct {
     int block;        /* 0: pairwise; b > 0: block-column ordering with blocks of b     */
     long max_steps;   /* > 0: stop after this many outer steps (bounded timing sample)  */
     int nthreads;     /* OpenMP threads over the independent pairs of one step          */
+    int inner_sweeps; /* block > 0: 0 = block-oriented (each outer step annihilates the
+                         pivot block's off-diagonal once, Sec. 5); k > 0 = full-block
+                         (each outer step diagonalises the pivot block by sweeps of the
+                         pointwise method over its 2b columns until one applies no
+                         rotation, at most k, Sec. 6)                                  */
 } orc_params;
 
 typedef struct {
@@ -50,6 +55,7 @@ typedef struct {
     long skips;       /* pair visits skipped by eq. 2.3                                 */
     long steps;       /* outer steps executed                                           */
     int r;            /* bordered order                                                 */
+    long inner;       /* full-block: inner sweeps executed, over all pivot blocks       */
 } orc_info;
 
 /* 2x2 pieces (exposed for pinning tests and bit-exact comparisons). */

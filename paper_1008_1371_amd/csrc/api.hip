@@ -224,6 +224,7 @@ void hsvd_default_params(hsvd_params *prm)
     prm->tol = 0.0;
     prm->t_thresh = 0.0;
     prm->graph = 1;
+    prm->inner_sweeps = 0;
 }
 
 hsvd_status hsvd_init(hsvd_ctx **out, int device, void *hip_stream)
@@ -434,12 +435,15 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
     if (V && !prm.want_v) return HSVD_E_INVAL;
     const bool mixed = prm.precision == HSVD_MIXED;
     if (mixed && prm.algo == HSVD_PAIRWISE) return HSVD_E_INVAL;
+    if (prm.inner_sweeps < 0 || prm.inner_sweeps > 100) return HSVD_E_INVAL;
+    const bool full_block = prm.inner_sweeps > 0;
+    if (full_block && prm.algo == HSVD_PAIRWISE) return HSVD_E_INVAL;
     // The block path needs at least two blocks of b columns; AUTO takes the
     // autotuner's choice for n's size bucket, else the block path from n >= 512;
-    // the mixed path always runs blocked.
+    // the mixed path and the full-block method always run blocked.
     const hsvd_ctx::Tune &tn = ctx->tune[size_bucket(n)];
-    const bool tuned = prm.algo == HSVD_AUTO && prm.block == 0 && tn.valid;
-    const bool block = mixed || prm.algo == HSVD_BLOCK ||
+    const bool tuned = prm.algo == HSVD_AUTO && prm.block == 0 && !full_block && tn.valid;
+    const bool block = mixed || full_block || prm.algo == HSVD_BLOCK ||
                        (prm.algo == HSVD_AUTO && (tuned ? tn.algo == HSVD_BLOCK : n >= 512));
     const int b = block ? block_width() : 0;
     const int mult = block ? 2 * b : 2;
@@ -583,6 +587,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             const double tol32 = fmax(tol, sqrt((double)r) * 0x1p-23);
             fa.tol = tol32;
             fa.tthresh = sqrt(tol32) / 2.0;
+            fa.inner_sweeps = prm.inner_sweeps;
             double prev = 1.0;
             int sw32 = 0;
             // Leave FP32 when the largest tangent of a sweep is at the FP32
@@ -639,6 +644,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             ba.ctl = w.ctl;
             ba.tol = tol;
             ba.tthresh = tthresh;
+            ba.inner_sweeps = prm.inner_sweeps;
             auto done64 = [](const SweepResult &sr) { return (sr.code & 2) == 0; };  // eq. (4.2)
             status = block_sweeps<double>(ctx, w, ba, w.G, pairs, steps_per_sweep, max_sweeps, prm.sort != 0, r, p,
                                           ldg, gstep, HSVD_K_BLOCK_GRAM, kms, klaunch, ktimed, sweeps, steps, last,
@@ -865,6 +871,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
     if (prm.precision != HSVD_FP64) return HSVD_E_INVAL;
     if (prm.ordering != HSVD_ORD_MODMOD && prm.ordering != HSVD_ORD_ROUNDROBIN) return HSVD_E_INVAL;
     if (prm.block != 0 && prm.block != block_width()) return HSVD_E_INVAL;
+    if (prm.inner_sweeps < 0 || prm.inner_sweeps > 100) return HSVD_E_INVAL;
     const bool want_v = prm.want_v != 0;
     if (V && !want_v) return HSVD_E_INVAL;
     for (int k = 0; k < batch; ++k)
@@ -1003,6 +1010,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         ba.ctl = g.ctl;
         ba.tol = 0.0;
         ba.tthresh = 0.0;
+        ba.inner_sweeps = prm.inner_sweeps;
         ba.nprob = K;
         ba.done = g.done;
         ba.pvec = g.p;

@@ -229,160 +229,197 @@ __global__ __launch_bounds__(256) void block_gram_kernel(BlockArgsT<T> a)
 }
 
 // ---------------------------------------------------------------------------
-// Inner solve of one block pair.
+// Inner solve of one block pair over all pairs of its 2b columns: sweeps of the
+// circle method over 2b indices (2b - 1 inner steps of b pairs each).  One
+// sweep in the first outer step of a sweep of the block-oriented method;
+// repeated until a sweep applies no rotation (at most a.inner_sweeps) in every
+// outer step of the full-block method.
+//
+// A_P and W live in LDS.  At an inner step every local index belongs to
+// exactly one slot, so the 2x2 block (s1, s2) of A_P -- rows of slot s1's
+// pair, columns of slot s2's -- is read and written by thread (s1, s2) alone,
+// and W's columns of slot q by the 32 threads of that slot; the first wave
+// evaluates the b rotations.  Mirrored blocks apply row and column operations
+// in mirrored order (the transposed block runs the same column-then-row
+// sequence), so A_P stays exactly symmetric.  Two barriers per inner step.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void block_inner_kernel(BlockArgsT<T> a)
+__global__ __launch_bounds__(1024) void block_inner_circle_kernel(BlockArgsT<T> a)
 {
     __shared__ double A[kB2 * kLd];
     __shared__ double Wl[kB2 * kLd];
-    __shared__ double pt[kB], pc[kB], pht[kB];
-    __shared__ int px[kB], py[kB], prot[kB];
-    __shared__ int s_code, s_rot, s_skip, s_any;
-    __shared__ unsigned long long s_mask;  // local columns touched by a rotation
-    __shared__ double s_maxt[kB];
+    __shared__ double4 prm[kB];  // (t, c, t or -t, rotated) of each slot
+    __shared__ int2 pxy[kB];     // local indices (x < y) of each slot's pair
+    __shared__ int s_any, s_sweep_any;
     if (!bind_problem(a)) return;
     const int k = blockIdx.x;
+    const int tid = threadIdx.x;
     const int2 IJ = outer_pair(a, k);
-    const T *P = a.partial + (size_t)k * a.splits * (kB2 * kB2);
-    // Sum of the partial Grams in split order.  All splits of an entry are
-    // loaded before the sum starts, so the loads overlap.
-    for (int idx = threadIdx.x; idx < kB2 * kB2; idx += 256) {
-        const int x = idx / kB2, y = idx % kB2;
-        const int iu = min(x, y) * kB2 + max(x, y);  // the Gram kernel forms the upper triangle
-        double v[kMaxSplits];
+
+    // A_P = sum of the partial Grams in split order (upper-triangular tiles,
+    // vector loads), then every entry (x, y) taken from (min, max)
+    {
+        typedef T v4 __attribute__((ext_vector_type(4)));
+        constexpr int kChunk = 8;
+        const int x = tid >> 4, y0 = (tid & 15) * 4;
+        if ((y0 >> 4) >= (x >> 4)) {
+            const T *P = a.partial + (size_t)k * a.splits * (kB2 * kB2) + x * kB2 + y0;
+            double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+            for (int base = 0; base < a.splits; base += kChunk) {
+                v4 v[kChunk];
 #pragma unroll
-        for (int sp = 0; sp < kMaxSplits; ++sp)
-            v[sp] = sp < a.splits ? (double)P[(size_t)sp * (kB2 * kB2) + iu] : 0.0;
-        double s = v[0];
+                for (int q = 0; q < kChunk; ++q)
+                    v[q] = base + q < a.splits
+                               ? *reinterpret_cast<const v4 *>(P + (size_t)(base + q) * (kB2 * kB2))
+                               : v4{0, 0, 0, 0};
 #pragma unroll
-        for (int sp = 1; sp < kMaxSplits; ++sp)
-            if (sp < a.splits) s += v[sp];
-        A[x * kLd + y] = s;
-        Wl[x * kLd + y] = x == y ? 1.0 : 0.0;
+                for (int q = 0; q < kChunk; ++q)
+                    if (base + q < a.splits) {
+                        const bool first = base + q == 0;
+                        g0 = first ? (double)v[q][0] : g0 + (double)v[q][0];
+                        g1 = first ? (double)v[q][1] : g1 + (double)v[q][1];
+                        g2 = first ? (double)v[q][2] : g2 + (double)v[q][2];
+                        g3 = first ? (double)v[q][3] : g3 + (double)v[q][3];
+                    }
+            }
+            double *row = A + x * kLd + y0;
+            row[0] = g0;
+            row[1] = g1;
+            row[2] = g2;
+            row[3] = g3;
+        }
     }
-    if (threadIdx.x == 0) {
-        s_code = 0;
-        s_rot = 0;
-        s_skip = 0;
+    if (tid == 0) {
         s_any = 0;
-        s_mask = 0ull;
+        s_sweep_any = 0;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < kB2 * kB2; idx += 1024) {
+        const int x = idx >> 6, y = idx & 63;
+        if (x > y) A[x * kLd + y] = A[y * kLd + x];
+        Wl[x * kLd + y] = x == y ? 1.0 : 0.0;
     }
     __syncthreads();
 
-    const bool first = a.step == 0;
-    const int inner_steps = first ? kB2 - 1 : kB;
+    const int s1 = tid >> 5, s2 = tid & 31;  // A block of this thread
+    const bool cf = s1 <= s2;
+    const int wq = tid & 31, wr = tid >> 5;  // W: slot wq, rows wr and wr + 32
     int code = 0, nrot = 0, nskip = 0, rank = 0;
     double maxt = 0.0;
     unsigned long long tmask = 0ull;
-    for (int u = 0; u < inner_steps; ++u) {
-        if (threadIdx.x < kB) {
-            const int q = threadIdx.x;
-            const int2 xy = block_inner_pair(q, u, first, kB);
-            const int x = xy.x, y = xy.y;
-            const double axx = A[x * kLd + x], ayy = A[y * kLd + y], axy = A[x * kLd + y];
-            double t = 0.0, c = 1.0;
-            int rot = 0;
-            if (rel_orthogonal_sq(axx, ayy, axy, a.tol, a.tol * a.tol)) {
-                ++nskip;
-            } else {
-                const int px_ = local_pos(x, IJ.x, IJ.y), py_ = local_pos(y, IJ.x, IJ.y);
-                const int hyp = ((px_ < a.p) == (py_ < a.p)) ? -1 : 1;
-                if (rotation_params_fast(axx, ayy, axy, hyp, t, c)) {
-                    rank = 1;
-                    t = 0.0;
-                    c = 1.0;
+    const double tol2 = a.tol * a.tol;
+    const int nsweeps = a.inner_sweeps > 0 ? a.inner_sweeps : 1;
+    int mark = 0;  // index of the current inner step, from 1
+    for (int sw = 0; sw < nsweeps; ++sw) {
+        for (int u = 0; u < kB2 - 1; ++u) {
+            ++mark;
+            if (tid < kB) {
+                const int q = tid;
+                const int2 xy = block_inner_pair(q, u, true, kB);
+                const int x = xy.x, y = xy.y;
+                const double axx = A[x * kLd + x], ayy = A[y * kLd + y], axy = A[x * kLd + y];
+                double t = 0.0, c = 1.0, h = 0.0;
+                int rot = 0;
+                if (rel_orthogonal_sq(axx, ayy, axy, a.tol, tol2)) {
+                    ++nskip;
                 } else {
-                    rot = 1;
-                    ++nrot;
-                    code |= rotation_code(t, a.tthresh);
-                    maxt = fmax(maxt, fabs(t));
-                    pht[q] = hyp < 0 ? -t : t;
+                    const int px_ = local_pos(x, IJ.x, IJ.y), py_ = local_pos(y, IJ.x, IJ.y);
+                    const int hyp = ((px_ < a.p) == (py_ < a.p)) ? -1 : 1;
+                    if (rotation_params_fast(axx, ayy, axy, hyp, t, c)) {
+                        rank = 1;
+                        t = 0.0;
+                        c = 1.0;
+                    } else {
+                        rot = 1;
+                        ++nrot;
+                        code |= rotation_code(t, a.tthresh);
+                        maxt = fmax(maxt, fabs(t));
+                        h = hyp < 0 ? -t : t;
+                        tmask |= (1ull << x) | (1ull << y);
+                    }
+                }
+                prm[q] = make_double4(t, c, h, rot ? 1.0 : 0.0);
+                pxy[q] = xy;
+                if (rot) {
+                    s_any = mark;
+                    s_sweep_any = sw + 1;
                 }
             }
-            if (!rot) pht[q] = 0.0;
-            if (rot) tmask |= (1ull << x) | (1ull << y);
-            pt[q] = t;
-            pc[q] = c;
-            px[q] = x;
-            py[q] = y;
-            prot[q] = rot;
-            if (rot) s_any = u + 1;
-        }
-        __syncthreads();
-        if (s_any != u + 1) continue;  // no rotation in this inner step: A and W unchanged
-        // A <- R^T A R on the 2x2 blocks (k1 <= k2), mirrored to keep A symmetric.
-        for (int blk = threadIdx.x; blk < kB * kB; blk += 256) {
-            const int k1 = blk / kB, k2 = blk % kB;
-            if (k1 > k2) continue;
-            const int x1 = px[k1], y1 = py[k1], x2 = px[k2], y2 = py[k2];
-            const double t1 = pt[k1], c1 = pc[k1], h1 = pht[k1];
-            const double t2 = pt[k2], c2 = pc[k2], h2 = pht[k2];
-            double e00 = A[x1 * kLd + x2], e01 = A[x1 * kLd + y2];
-            double e10 = A[y1 * kLd + x2], e11 = A[y1 * kLd + y2];
-            // columns (x2, y2)
-            double f00 = fma(h2, e01, e00) * c2, f01 = fma(t2, e00, e01) * c2;
-            double f10 = fma(h2, e11, e10) * c2, f11 = fma(t2, e10, e11) * c2;
-            // rows (x1, y1)
-            e00 = fma(h1, f10, f00) * c1;
-            e10 = fma(t1, f00, f10) * c1;
-            e01 = fma(h1, f11, f01) * c1;
-            e11 = fma(t1, f01, f11) * c1;
-            if (k1 == k2) {
-                if (prot[k1]) {
-                    e01 = 0.0;
-                    e10 = 0.0;
+            __syncthreads();
+            // no rotation in this inner step: A and W unchanged.  The first wave
+            // may already be writing the next step's mark, but only after this
+            // step had none, so a late reader still sees a mismatch.
+            if (s_any != mark) continue;
+            {
+                // A block: rows (x1, y1) by slot s1, columns (x2, y2) by slot s2
+                const int2 r1 = pxy[s1], r2 = pxy[s2];
+                const double4 pa = prm[cf ? s2 : s1], pq = prm[cf ? s1 : s2];
+                const double e00 = A[r1.x * kLd + r2.x], e01 = A[r1.x * kLd + r2.y];
+                const double e10 = A[r1.y * kLd + r2.x], e11 = A[r1.y * kLd + r2.y];
+                const double x01 = cf ? e01 : e10, x10 = cf ? e10 : e01;
+                const double f00 = fma(pa.z, x01, e00) * pa.y, f01 = fma(pa.x, e00, x01) * pa.y;
+                const double f10 = fma(pa.z, e11, x10) * pa.y, f11 = fma(pa.x, x10, e11) * pa.y;
+                const double y00 = fma(pq.z, f10, f00) * pq.y, y10 = fma(pq.x, f00, f10) * pq.y;
+                const double y01 = fma(pq.z, f11, f01) * pq.y, y11 = fma(pq.x, f01, f11) * pq.y;
+                double o01 = cf ? y01 : y10, o10 = cf ? y10 : y01;
+                if (s1 == s2 && pa.w != 0.0) {
+                    o01 = 0.0;
+                    o10 = 0.0;
                 }
-                A[x1 * kLd + x1] = e00;
-                A[y1 * kLd + y1] = e11;
-                A[x1 * kLd + y1] = e01;
-                A[y1 * kLd + x1] = e01;
-            } else {
-                A[x1 * kLd + x2] = e00;
-                A[x1 * kLd + y2] = e01;
-                A[y1 * kLd + x2] = e10;
-                A[y1 * kLd + y2] = e11;
-                A[x2 * kLd + x1] = e00;
-                A[y2 * kLd + x1] = e01;
-                A[x2 * kLd + y1] = e10;
-                A[y2 * kLd + y1] = e11;
+                A[r1.x * kLd + r2.x] = y00;
+                A[r1.x * kLd + r2.y] = o01;
+                A[r1.y * kLd + r2.x] = o10;
+                A[r1.y * kLd + r2.y] = y11;
             }
+            {
+                // W <- W R on the columns of slot wq, rows wr and wr + 32
+                const int2 xy = pxy[wq];
+                const double4 pw = prm[wq];
+                if (pw.w != 0.0) {
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2) {
+                        const int w = wr + 32 * h2;
+                        const double wx = Wl[w * kLd + xy.x], wy = Wl[w * kLd + xy.y];
+                        Wl[w * kLd + xy.x] = fma(pw.z, wy, wx) * pw.y;
+                        Wl[w * kLd + xy.y] = fma(pw.x, wx, wy) * pw.y;
+                    }
+                }
+            }
+            __syncthreads();
         }
-        // W <- W R on the columns of each pair.
-        for (int it = threadIdx.x; it < kB2 * kB; it += 256) {
-            const int q = it / kB2, w = it % kB2;
-            if (!prot[q]) continue;
-            const int x = px[q], y = py[q];
-            const double wx = Wl[w * kLd + x], wy = Wl[w * kLd + y];
-            Wl[w * kLd + x] = fma(pht[q], wy, wx) * pc[q];
-            Wl[w * kLd + y] = fma(pt[q], wx, wy) * pc[q];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < kB) {
-        if (code) atomicOr(&s_code, code);
-        if (nrot) atomicAdd(&s_rot, nrot);
-        if (nskip) atomicAdd(&s_skip, nskip);
-        if (rank) atomicOr(&a.ctl->rank, 1);
-        if (tmask) atomicOr(&s_mask, tmask);
-        s_maxt[threadIdx.x] = maxt;
+        // a sweep without rotations: the block is diagonal.  s_sweep_any only
+        // grows (the first wave starts sweep sw + 1, and may raise it, only
+        // after sweep sw rotated), so every thread takes the same decision
+        // even if it reads the flag late.
+        if (s_sweep_any < sw + 1) break;
     }
     T *Wg = a.W + (size_t)k * (kB2 * kB2);
-    for (int idx = threadIdx.x; idx < kB2 * kB2; idx += 256) {
-        const int x = idx / kB2, y = idx % kB2;
-        Wg[idx] = (T)Wl[x * kLd + y];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = a.maxt[k];
-        for (int q = 0; q < kB; ++q) m = fmax(m, s_maxt[q]);
-        a.maxt[k] = m;
-        a.C[k] |= s_code;
-        a.nrot[k] += (unsigned)s_rot;
-        a.nskip[k] += (unsigned)s_skip;
-        a.nact[k] += s_rot > 0 ? 1u : 0u;
-        a.ntc[k] += (unsigned)__popcll(s_mask);
-        a.active[k] = s_mask;
+    for (int idx = tid; idx < kB2 * kB2; idx += 1024) Wg[idx] = (T)Wl[(idx >> 6) * kLd + (idx & 63)];
+    if (tid < 64) {
+        // counters of the b slots, reduced within the first wave
+        unsigned rot_sum = (unsigned)nrot, skip_sum = (unsigned)nskip;
+        unsigned mlo = (unsigned)tmask, mhi = (unsigned)(tmask >> 32);
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            code |= __shfl_xor(code, m, 64);
+            rank |= __shfl_xor(rank, m, 64);
+            rot_sum += __shfl_xor(rot_sum, m, 64);
+            skip_sum += __shfl_xor(skip_sum, m, 64);
+            maxt = fmax(maxt, __shfl_xor(maxt, m, 64));
+            mlo |= __shfl_xor(mlo, m, 64);
+            mhi |= __shfl_xor(mhi, m, 64);
+        }
+        if (tid == 0) {
+            const unsigned long long mask = ((unsigned long long)mhi << 32) | mlo;
+            if (rank) atomicOr(&a.ctl->rank, 1);
+            a.maxt[k] = fmax(a.maxt[k], maxt);
+            a.C[k] |= code;
+            a.nrot[k] += rot_sum;
+            a.nskip[k] += skip_sum;
+            a.nact[k] += rot_sum > 0 ? 1u : 0u;
+            a.ntc[k] += (unsigned)__popcll(mask);
+            a.active[k] = mask;
+        }
     }
 }
 
@@ -849,8 +886,8 @@ hipError_t launch_block_gram(hipStream_t st, const BlockArgsT<T> &a)
 template <typename T>
 hipError_t launch_block_inner(hipStream_t st, const BlockArgsT<T> &a)
 {
-    if (a.step == 0)
-        block_inner_kernel<T><<<dim3(a.nb / 2, 1, a.nprob), 256, 0, st>>>(a);
+    if (a.step == 0 || a.inner_sweeps > 0)
+        block_inner_circle_kernel<T><<<dim3(a.nb / 2, 1, a.nprob), 1024, 0, st>>>(a);
     else
         block_inner_cross_kernel<T><<<dim3(a.nb / 2, 1, a.nprob), 1024, 0, st>>>(a);
     return hipGetLastError();

@@ -317,6 +317,7 @@ struct BlockArgsT {
     const int4 *S_in;        // outer stepper state of this step
     int4 *S_out;             // state of the next step (written by the update kernel)
     int ordering, step;      // step: outer step index inside the sweep
+    int inner_sweeps = 0;    // 0: block-oriented; k > 0: full-block, at most k inner sweeps per pivot block
     T *partial;
     int splits, rows_per_split;
     T *W;

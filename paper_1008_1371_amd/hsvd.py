@@ -31,7 +31,8 @@ class hsvd_params(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("algo", ctypes.c_int), ("ordering", ctypes.c_int),
                 ("block", ctypes.c_int), ("sort", ctypes.c_int), ("want_v", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("tol", ctypes.c_double),
-                ("t_thresh", ctypes.c_double), ("graph", ctypes.c_int)]
+                ("t_thresh", ctypes.c_double), ("graph", ctypes.c_int),
+                ("inner_sweeps", ctypes.c_int)]
 
 
 NKERNELS = 8
