@@ -77,6 +77,12 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--batched", type=int, default=0,
                     help="also time the batched solver on this many small problems")
+    ap.add_argument("--inner-sweeps", type=int, default=0,
+                    help="block modes: 0 = block-oriented method; k > 0 = full-block method with at most "
+                         "k inner sweeps per pivot block")
+    ap.add_argument("--no-v", action="store_true",
+                    help="eigenvalues / singular values and U only: V is not returned (the mixed path "
+                         "still carries V internally through its FP32 phase)")
     ap.add_argument("--max-sweeps", type=int, default=0,
                     help="stop each solve after this many sweeps (profiling runs only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -233,16 +239,22 @@ def main():
     out = dict(
         sigma=torch.empty(n, dtype=torch.float64, device=dev),
         U=torch.empty((n, n), dtype=torch.float64, device=dev).t(),
-        V=torch.empty((n, n), dtype=torch.float64, device=dev).t(),
+        V=None if args.no_v else torch.empty((n, n), dtype=torch.float64, device=dev).t(),
         **{"lambda": torch.empty(n, dtype=torch.float64, device=dev)},
         perm=torch.empty(n, dtype=torch.int32, device=dev),
     )
     check = args.max_sweeps <= 0
     peaks = [FP64_PEAK_TFLOPS] * 4 + [FP32_PEAK_TFLOPS] * 3 + [FP64_PEAK_TFLOPS]
 
+    def variant(mode):
+        # the counter measurements hold for the default variant of a mode only
+        return mode + ("/full-block" if args.inner_sweeps > 0 else "") + ("/no-v" if args.no_v else "")
+
     def params(mode):
         prm = H.hsvd_default_params(algo=H.PAIRWISE if mode == "pairwise" else H.BLOCK,
-                                    precision=H.MIXED if mode == "mixed" else H.FP64)
+                                    precision=H.MIXED if mode == "mixed" else H.FP64,
+                                    want_v=0 if args.no_v else 1,
+                                    inner_sweeps=0 if mode == "pairwise" else args.inner_sweeps)
         if args.max_sweeps > 0:
             prm.max_sweeps = args.max_sweeps
         return prm
@@ -270,11 +282,14 @@ def main():
         "dtype": "f32+f64" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "p": p, "path": f"{head}",
-                   "block": last["block"], "ordering": "modmod", "sort": 1, "want_v": 1,
+                   "block": last["block"], "ordering": "modmod", "sort": 1, "want_v": 0 if args.no_v else 1,
+                   "method": ("pairwise" if head == "pairwise" else
+                              "full-block" if args.inner_sweeps > 0 else "block-oriented"),
+                   "inner_sweeps": args.inner_sweeps,
                    "tol": 1e-15 * n, "sweeps_fp32": last["sweeps_fp32"], "sweeps_fp64": last["sweeps"],
                    "reorth_iters": last["reorth_iters"], "rotations": last["rotations"],
                    "steps_per_solve": last["steps"]},
-        "roofline": roofline(infos, H.KERNEL_NAMES, peaks, args.workload, head),
+        "roofline": roofline(infos, H.KERNEL_NAMES, peaks, args.workload, variant(head)),
     }
     if acc is not None:
         line["accuracy"] = acc
@@ -282,7 +297,7 @@ def main():
         if mode == head:
             continue
         line[mode] = {"value": 1000.0 / m_ms, "ms_per_step": m_ms, "sweeps": m_infos[-1]["sweeps"],
-                      "roofline": roofline(m_infos, H.KERNEL_NAMES, peaks, args.workload, mode),
+                      "roofline": roofline(m_infos, H.KERNEL_NAMES, peaks, args.workload, variant(mode)),
                       "accuracy": m_acc}
         line["speedup_vs_" + mode] = m_ms / ms
     if args.batched > 0:
