@@ -121,15 +121,17 @@ Layout make_layout(int n, int r, int ldg, bool want_v, int pairs, int splits, in
     L.off_ctl = take(sizeof(Ctl));
     const size_t bb = (size_t)b2 * b2;
     L.off_P = take(sizeof(double) * (size_t)pairs * splits * bb);
-    L.off_W = take(sizeof(double) * (size_t)pairs * bb);
-    L.off_active = take(sizeof(unsigned long long) * (size_t)pairs);
+    // W and the touched-column masks are double-buffered by step parity: the
+    // V update of a step runs inside the next step's inner launch
+    L.off_W = take(sizeof(double) * (size_t)pairs * bb * 2);
+    L.off_active = take(sizeof(unsigned long long) * (size_t)pairs * 2);
     L.off_S2 = take(sizeof(int4) * 2 * (size_t)pairs);
     L.mixed = mixed;
     const size_t mat = (size_t)ldg * r;
     L.off_G32 = take(mixed ? sizeof(float) * mat : 0);
     L.off_V32 = take(mixed ? sizeof(float) * mat : 0);
     L.off_P32 = take(mixed ? sizeof(float) * (size_t)pairs * splits * bb : 0);
-    L.off_W32 = take(mixed ? sizeof(float) * (size_t)pairs * bb : 0);
+    L.off_W32 = take(mixed ? sizeof(float) * (size_t)pairs * bb * 2 : 0);
     L.off_T1 = take(mixed ? sizeof(double) * mat : 0);
     L.off_T2 = take(mixed ? sizeof(double) * mat : 0);
     L.bytes = o;
@@ -307,12 +309,38 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
 {
     hipStream_t st = ctx->stream;
     hipEvent_t *ev = ctx->events.data();
+    hipEvent_t *evv = ev + 4 + 4 * steps_per_sweep;  // around the V update of a sweep's last step
     finished = false;
+    // W and the masks alternate between two buffers by step parity.  With V
+    // accumulated by the block-oriented method, the V half of a step's update
+    // runs as extra workgroups of the next step's inner launch (on the CUs the
+    // inner solves leave idle; the next Gram needs G alone), and the last
+    // step's in an update launch of its own at the end of the sweep.
+    const size_t wstride = (size_t)pairs * (2 * block_width()) * (2 * block_width());
+    T *const Wb = ba.W;
+    unsigned long long *const Ab = ba.active;
+    const bool fuse = ba.V != nullptr && ba.inner_sweeps == 0 && ba.nprob <= 1;
+    int cus = 0;
+    if (fuse && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
+        return HSVD_E_DEVICE;
+    ba.vrows = fuse ? v_update_role_rows(pairs, ldg, cus) : 0;
+    const int vwgs = fuse ? v_update_role_wgs(pairs, ldg, ba.vrows) : 0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         for (int k = 0; k < steps_per_sweep; ++k, ++gstep) {
+            const int par = (int)(gstep & 1);
             ba.step = k;
-            ba.S_in = w.S2 + (gstep & 1) * pairs;
-            ba.S_out = w.S2 + ((gstep + 1) & 1) * pairs;
+            ba.S_in = w.S2 + par * pairs;
+            ba.S_out = w.S2 + (par ^ 1) * pairs;
+            ba.W = Wb + par * wstride;
+            ba.active = Ab + par * pairs;
+            ba.vprev_wgs = 0;
+            if (fuse && k > 0) {
+                ba.vprev_wgs = vwgs;
+                ba.W_prev = Wb + (par ^ 1) * wstride;
+                ba.active_prev = Ab + (par ^ 1) * pairs;
+                ba.S_prev = w.S2 + (par ^ 1) * pairs;  // the previous step's S_in: rewritten by this step's update
+                ba.step_prev = k - 1;
+            }
             hipEvent_t *e = ev + 4 + 4 * k;
             const bool tm = k % kTimeEvery == 0;
             if (tm) HSVD_TRY(hipEventRecord(e[0], st));
@@ -320,8 +348,20 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
             if (tm) HSVD_TRY(hipEventRecord(e[1], st));
             HSVD_TRY(launch_block_inner<T>(st, ba));
             if (tm) HSVD_TRY(hipEventRecord(e[2], st));
-            HSVD_TRY(launch_block_update<T>(st, ba));
+            HSVD_TRY(launch_block_update<T>(st, ba, fuse ? UPD_G : UPD_BOTH));
             if (tm) HSVD_TRY(hipEventRecord(e[3], st));
+        }
+        if (fuse) {
+            const int par = (int)((gstep - 1) & 1);
+            BlockArgsT<T> lv = ba;
+            lv.step = steps_per_sweep - 1;
+            lv.S_in = w.S2 + par * pairs;
+            lv.W = Wb + par * wstride;
+            lv.active = Ab + par * pairs;
+            lv.vprev_wgs = 0;
+            HSVD_TRY(hipEventRecord(evv[0], st));
+            HSVD_TRY(launch_block_update<T>(st, lv, UPD_V));
+            HSVD_TRY(hipEventRecord(evv[1], st));
         }
         for (int q = 0; q < 3; ++q) klaunch[kbase + q] += steps_per_sweep;
         // the kept diagonal: fresh column norms of the updated columns
@@ -348,6 +388,13 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
                 kms[kbase + q] += first[q] + rest[q] * scale;
                 ktimed[kbase + q] += 1 + nrest;
             }
+            if (fuse) {
+                float ms = 0.f;
+                HSVD_TRY(hipEventElapsedTime(&ms, evv[0], evv[1]));
+                kms[kbase + 2] += ms;
+                ktimed[kbase + 2] += 1;
+                klaunch[kbase + 2] += 1;
+            }
         }
         ++sweeps;
         last.code = ctx->host_ctl->code;
@@ -357,12 +404,20 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
             fprintf(stderr, "hsvd sweep %d (%s): max|t| %.3e code %d rotations %llu skips %llu\n", sweeps,
                     sizeof(T) == 4 ? "fp32" : "fp64", last.maxt, last.code,
                     (unsigned long long)ctx->host_ctl->rot, (unsigned long long)ctx->host_ctl->skip);
-        if (last.rank) return HSVD_E_RANK;
+        if (last.rank) {
+            ba.W = Wb;
+            ba.active = Ab;
+            ba.vprev_wgs = 0;
+            return HSVD_E_RANK;
+        }
         if (done(last)) {
             finished = true;
             break;
         }
     }
+    ba.W = Wb;
+    ba.active = Ab;
+    ba.vprev_wgs = 0;
     return HSVD_OK;
 }
 
@@ -479,7 +534,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
     const Layout L = make_layout(n, r, ldg, acc_v, pairs, splits, block ? 2 * b : 0, mixed);
     hsvd_status s = ensure_ws(ctx, L.bytes);
     if (s != HSVD_OK) return s;
-    const int nev = block ? 4 + 4 * steps_per_sweep : 4;
+    const int nev = block ? 4 + 4 * steps_per_sweep + 2 : 4;
     s = ensure_events(ctx, (size_t)nev);
     if (s != HSVD_OK) return s;
     const Workspace w = carve(ctx->ws, L);
@@ -706,12 +761,16 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
                 const double visits = (prec == 0 ? st64 : st32) * pairs;
                 const double tcols = prec == 0 ? tc_all - (double)tcol32 : (double)tcol32;
                 const double vm = prec == 0 ? vmul : 2.0;
+                // with V carried by the block-oriented method, V's half of the
+                // update runs inside the inner launches and is counted there
+                const double vin = (vm > 1.0 && prm.inner_sweeps == 0) ? 1.0 : 0.0;
                 info->kernel_bytes[kb] = visits * esz * b2 * rows;
                 info->kernel_flops[kb] = visits * 2.0 * b2 * b2 * rows;
-                info->kernel_bytes[kb + 1] = visits * (double)(splits * esz + 2 * esz) * b2 * b2;
-                info->kernel_flops[kb + 1] = 0.0;
-                info->kernel_bytes[kb + 2] = tcols * 2.0 * esz * rows * vm;
-                info->kernel_flops[kb + 2] = tcols * 2.0 * b2 * rows * vm;
+                info->kernel_bytes[kb + 1] = visits * (double)(splits * esz + 2 * esz) * b2 * b2 +
+                                             vin * tcols * 2.0 * esz * rows;
+                info->kernel_flops[kb + 1] = vin * tcols * 2.0 * b2 * rows;
+                info->kernel_bytes[kb + 2] = tcols * 2.0 * esz * rows * (vm - vin);
+                info->kernel_flops[kb + 2] = tcols * 2.0 * b2 * rows * (vm - vin);
             }
             if (mixed) {
                 const double rr = (double)r;

@@ -108,6 +108,11 @@ __device__ __forceinline__ int local_pos(int x, int I, int J)
     return x < kB ? I * kB + x : J * kB + (x - kB);
 }
 
+// V update of the previous outer step, run by extra workgroups of an inner
+// launch (defined with the update kernel).
+template <typename T>
+__device__ void v_update_role(const BlockArgsT<T> &a, int role);
+
 // ---------------------------------------------------------------------------
 // Gram: partial[k][split] = G_P(rows of split)^T G_P(rows of split)
 // ---------------------------------------------------------------------------
@@ -453,6 +458,10 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
     // A_P staging at the start, the two LR / RL exchange buffers in the loop
     __shared__ double buf[kB2 * kLd];
     __shared__ double4 prm[2][kB];  // (t, c, t or -t, rotated) of each slot
+    if ((int)blockIdx.x >= a.nb / 2) {
+        v_update_role(a, (int)blockIdx.x - a.nb / 2);
+        return;
+    }
     if (!bind_problem(a)) return;
     const int k = blockIdx.x;
     const int tid = threadIdx.x;
@@ -667,13 +676,14 @@ struct UpdCfg<double> {
 // rows (rotations only combine touched columns), so [G_T | V_T] <- [G_T | V_T]
 // W_TT is the whole update.  Same MFMA formulation as the full update with NC
 // columns, W_TT zero-padded to NC x NC; only the m touched columns are read
-// and written.
-template <typename T, int NC>
+// and written.  NT threads.
+template <typename T, int NC, int NT>
 __device__ __forceinline__ void update_compact(const BlockArgsT<T> &a, int k, T *__restrict__ M, int row_base,
                                                int nstrips, T *Wl, const int *cols, const int *tl, int m)
 {
+    constexpr int NW = NT / 64;
     const T *Wg = a.W + (size_t)k * (kB2 * kB2);
-    for (int idx = threadIdx.x; idx < NC * NC; idx += 256) {
+    for (int idx = threadIdx.x; idx < NC * NC; idx += NT) {
         const int i = idx / NC, j = idx % NC;
         Wl[idx] = (i < m && j < m) ? Wg[tl[i] * kB2 + tl[j]] : T(0);
     }
@@ -685,7 +695,7 @@ __device__ __forceinline__ void update_compact(const BlockArgsT<T> &a, int k, T 
     const unsigned row_off = (unsigned)(row_base + lr) * (unsigned)sizeof(T);
     const unsigned col_bytes = (unsigned)a.ldg * (unsigned)sizeof(T);
 #pragma unroll 1
-    for (int strip = wave; strip < nstrips; strip += 4) {
+    for (int strip = wave; strip < nstrips; strip += NW) {
         const unsigned rb = (unsigned)(strip * 16) * (unsigned)sizeof(T) + row_off;
         T bv[KK];
 #pragma unroll
@@ -711,25 +721,17 @@ __device__ __forceinline__ void update_compact(const BlockArgsT<T> &a, int k, T 
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256, UpdCfg<T>::min_blocks) void block_update_kernel(BlockArgsT<T> a)
+// Rows [row_base, row_base + 16 nstrips) of the 2b columns of block pair k
+// in M (G or V) <- themselves times W, by NT threads; mask = the pair's
+// touched local columns (nonzero).  kWLds: W re-read from LDS for every
+// 16-row strip with the next strip's rows prefetched into registers when
+// kPrefetch (else the compiler keeps all 64 W operands in registers across
+// strips); kLd: LDS row stride of W.  Every thread must call it (barriers).
+template <typename T, int NT, bool kWLds, bool kPrefetch, int kLd>
+__device__ __forceinline__ void update_rows(const BlockArgsT<T> &a, int k, T *__restrict__ M, int row_base,
+                                            int nstrips, unsigned long long mask, T *Wl, int *cols, int *tl)
 {
-    constexpr int kRows = UpdCfg<T>::rows, kUpdLd = UpdCfg<T>::ld;
-    constexpr bool kWLds = UpdCfg<T>::w_lds;
-    __shared__ T Wl[kB2 * kUpdLd];
-    __shared__ int cols[kB2];
-    __shared__ int tl[kB2];
-    const int k = blockIdx.x;
-    const int tiles_g = (a.ldg + kRows - 1) / kRows;
-    const int t = blockIdx.y;
-    if (t == 0 && blockIdx.z == 0 && threadIdx.x == 0 && a.ordering == HSVD_ORD_MODMOD)
-        a.S_out[k] = modmod_next(a.S_in[k], a.nb);
-    if (!bind_problem(a)) return;
-    const unsigned long long mask = a.active[k];
-    if (!mask) return;  // no rotation in this pair: W = I
-    T *__restrict__ M = t < tiles_g ? a.G : a.V;
-    const int row_base = (t < tiles_g ? t : t - tiles_g) * kRows;
-    const int nstrips = min(kRows, a.ldg - row_base) / 16;
+    constexpr int NW = NT / 64;
     const int2 IJ = outer_pair(a, k);
     const int m = __popcll(mask);
     if (m <= 32) {
@@ -741,14 +743,14 @@ __global__ __launch_bounds__(256, UpdCfg<T>::min_blocks) void block_update_kerne
         }
         __syncthreads();
         if (m <= 16)
-            update_compact<T, 16>(a, k, M, row_base, nstrips, Wl, cols, tl, m);
+            update_compact<T, 16, NT>(a, k, M, row_base, nstrips, Wl, cols, tl, m);
         else
-            update_compact<T, 32>(a, k, M, row_base, nstrips, Wl, cols, tl, m);
+            update_compact<T, 32, NT>(a, k, M, row_base, nstrips, Wl, cols, tl, m);
         return;
     }
     if (threadIdx.x < kB2) cols[threadIdx.x] = a.rho[local_pos(threadIdx.x, IJ.x, IJ.y)];
     const T *Wg = a.W + (size_t)k * (kB2 * kB2);
-    for (int idx = threadIdx.x; idx < kB2 * kB2; idx += 256) Wl[(idx / kB2) * kUpdLd + idx % kB2] = Wg[idx];
+    for (int idx = threadIdx.x; idx < kB2 * kB2; idx += NT) Wl[(idx / kB2) * kLd + idx % kB2] = Wg[idx];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -764,19 +766,20 @@ __global__ __launch_bounds__(256, UpdCfg<T>::min_blocks) void block_update_kerne
         for (int kk = 0; kk < 16; ++kk)
             bv[kk] = *reinterpret_cast<const T *>(base + ((unsigned)cp[4 * kk + lk] * col_bytes + rb));
     };
+    constexpr bool kPre = kWLds && kPrefetch;
     T bv[16], nx[16];
-    if (kWLds && wave < nstrips) load(wave, bv, cols);
+    if (kPre && wave < nstrips) load(wave, bv, cols);
 #pragma unroll 1
-    for (int strip = wave; strip < nstrips; strip += 4) {
+    for (int strip = wave; strip < nstrips; strip += NW) {
         // With kWLds, the opaque zero wz keeps the compiler from hoisting the
         // column offsets and the 64 W operands into registers across strips.
         int wz = 0;
         if (kWLds) asm volatile("" : "+v"(wz));
-        if (kWLds)  // next strip in flight during the products; the last re-reads its own rows
-            load(strip + 4 < nstrips ? strip + 4 : strip, nx, cols + wz);
+        if (kPre)  // next strip in flight during the products; the last re-reads its own rows
+            load(strip + NW < nstrips ? strip + NW : strip, nx, cols + wz);
         else
-            load(strip, bv, cols);
-        const T *Wp = Wl + wz + lk * kUpdLd + lr;
+            load(strip, bv, cols + wz);
+        const T *Wp = Wl + wz + lk * kLd + lr;
         typename MF<T>::acc acc[4];
 #pragma unroll
         for (int yt = 0; yt < 4; ++yt) acc[yt] = MF<T>::zero();
@@ -785,7 +788,7 @@ __global__ __launch_bounds__(256, UpdCfg<T>::min_blocks) void block_update_kerne
 #pragma unroll
             for (int yt = 0; yt < 4; ++yt) {
                 // A(i = y, k = x) = W(x, y), x = 4kk + lk, y = 16yt + lr
-                const T aw = Wp[4 * kk * kUpdLd + yt * 16];
+                const T aw = Wp[4 * kk * kLd + yt * 16];
                 acc[yt] = MF<T>::mma(aw, bv[kk], acc[yt]);
             }
         const int *cp = cols + wz;
@@ -796,11 +799,63 @@ __global__ __launch_bounds__(256, UpdCfg<T>::min_blocks) void block_update_kerne
             for (int v = 0; v < 4; ++v)
                 *reinterpret_cast<T *>(base + ((unsigned)cp[yt * 16 + MF<T>::row(lane, v)] * col_bytes + rb)) =
                     acc[yt][v];
-        if (kWLds) {
+        if (kPre) {
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk) bv[kk] = nx[kk];
         }
     }
+}
+
+// Tiles of the update kernel: rows [t * rows, (t + 1) * rows) of G for
+// t < tiles_g, of V after that; a.tile0 shifts blockIdx.y (G-only and V-only
+// launches).
+template <typename T>
+__global__ __launch_bounds__(256, UpdCfg<T>::min_blocks) void block_update_kernel(BlockArgsT<T> a)
+{
+    constexpr int kRows = UpdCfg<T>::rows, kUpdLd = UpdCfg<T>::ld;
+    __shared__ T Wl[kB2 * kUpdLd];
+    __shared__ int cols[kB2];
+    __shared__ int tl[kB2];
+    const int k = blockIdx.x;
+    const int tiles_g = (a.ldg + kRows - 1) / kRows;
+    const int t = blockIdx.y + a.tile0;
+    if (t == 0 && blockIdx.z == 0 && threadIdx.x == 0 && a.ordering == HSVD_ORD_MODMOD)
+        a.S_out[k] = modmod_next(a.S_in[k], a.nb);
+    if (!bind_problem(a)) return;
+    const unsigned long long mask = a.active[k];
+    if (!mask) return;  // no rotation in this pair: W = I
+    T *__restrict__ M = t < tiles_g ? a.G : a.V;
+    const int row_base = (t < tiles_g ? t : t - tiles_g) * kRows;
+    const int nstrips = min(kRows, a.ldg - row_base) / 16;
+    update_rows<T, 256, UpdCfg<T>::w_lds, true, kUpdLd>(a, k, M, row_base, nstrips, mask, Wl, cols, tl);
+}
+
+// V update of the previous outer step inside an inner-solve launch: workgroup
+// `role` (after the block pairs' own workgroups) takes rows [tile * a.vrows,
+// ...) of V for block pair role / tiles.  The inner solve holds only one
+// workgroup per block pair, most CUs are free meanwhile, and the next step's
+// Gram needs G alone, so V's half of the update runs here instead of after
+// the inner solve.  1024 threads: W from LDS (the 64 W operands do not fit
+// the register budget of a 1024-thread workgroup), prefetch for FP32 only.
+template <typename T>
+__device__ void v_update_role(const BlockArgsT<T> &a, int role)
+{
+    constexpr int kLdV = sizeof(T) == 8 ? kB2 + 8 : kB2 + 16;
+    __shared__ T Wl[kB2 * kLdV];
+    __shared__ int cols[kB2];
+    __shared__ int tl[kB2];
+    const int tiles = (a.ldg + a.vrows - 1) / a.vrows;
+    const int k = role / tiles, tile = role - k * tiles;
+    BlockArgsT<T> v = a;
+    v.W = a.W_prev;
+    v.active = a.active_prev;
+    v.S_in = a.S_prev;
+    v.step = a.step_prev;
+    const unsigned long long mask = v.active[k];
+    if (!mask) return;
+    const int row_base = tile * a.vrows;
+    const int nstrips = min(a.vrows, a.ldg - row_base) / 16;
+    update_rows<T, 1024, true, true, kLdV>(v, k, a.V, row_base, nstrips, mask, Wl, cols, tl);
 }
 
 // Outer stepper start (nb/2 slots, antidiagonal over blocks).
@@ -883,21 +938,51 @@ hipError_t launch_block_gram(hipStream_t st, const BlockArgsT<T> &a)
     return hipGetLastError();
 }
 
+// Rows of V per role workgroup: the V update of one step spread over about
+// the CUs that the inner solves leave free (multiples of 256 rows, one
+// 16-row strip per wave at least).
+int v_update_role_rows(int pairs, int ldg, int cus)
+{
+    const int free_cus = cus > pairs ? cus - pairs : 1;
+    const long long total = (long long)pairs * ldg;
+    int rows = (int)((total + free_cus - 1) / free_cus);
+    rows = (rows + 255) / 256 * 256;
+    return rows < ldg ? rows : ldg;
+}
+
+int v_update_role_wgs(int pairs, int ldg, int vrows) { return pairs * ((ldg + vrows - 1) / vrows); }
+
 template <typename T>
 hipError_t launch_block_inner(hipStream_t st, const BlockArgsT<T> &a)
 {
-    if (a.step == 0 || a.inner_sweeps > 0)
+    // only the cross steps carry V-update workgroups (the first step of a
+    // sweep has no previous step in it; the full-block method updates V in
+    // its update launches)
+    if (a.step == 0 || a.inner_sweeps > 0) {
+        if (a.vprev_wgs > 0) return hipErrorInvalidValue;
         block_inner_circle_kernel<T><<<dim3(a.nb / 2, 1, a.nprob), 1024, 0, st>>>(a);
-    else
-        block_inner_cross_kernel<T><<<dim3(a.nb / 2, 1, a.nprob), 1024, 0, st>>>(a);
+        return hipGetLastError();
+    }
+    if (a.vprev_wgs > 0 && a.nprob > 1) return hipErrorInvalidValue;
+    block_inner_cross_kernel<T><<<dim3(a.nb / 2 + a.vprev_wgs, 1, a.nprob), 1024, 0, st>>>(a);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_block_update(hipStream_t st, const BlockArgsT<T> &a)
+hipError_t launch_block_update(hipStream_t st, const BlockArgsT<T> &a, int which)
 {
-    const int tiles = ((a.ldg + UpdCfg<T>::rows - 1) / UpdCfg<T>::rows) * (a.V ? 2 : 1);
-    block_update_kernel<T><<<dim3(a.nb / 2, tiles, a.nprob), 256, 0, st>>>(a);
+    const int tiles_g = (a.ldg + UpdCfg<T>::rows - 1) / UpdCfg<T>::rows;
+    BlockArgsT<T> b = a;
+    int tiles = tiles_g * (a.V ? 2 : 1);
+    b.tile0 = 0;
+    if (which == UPD_G) {
+        tiles = tiles_g;
+    } else if (which == UPD_V) {
+        if (!a.V) return hipSuccess;
+        tiles = tiles_g;
+        b.tile0 = tiles_g;
+    }
+    block_update_kernel<T><<<dim3(a.nb / 2, tiles, a.nprob), 256, 0, st>>>(b);
     return hipGetLastError();
 }
 
@@ -912,8 +997,8 @@ template hipError_t launch_block_gram<double>(hipStream_t, const BlockArgsT<doub
 template hipError_t launch_block_gram<float>(hipStream_t, const BlockArgsT<float> &);
 template hipError_t launch_block_inner<double>(hipStream_t, const BlockArgsT<double> &);
 template hipError_t launch_block_inner<float>(hipStream_t, const BlockArgsT<float> &);
-template hipError_t launch_block_update<double>(hipStream_t, const BlockArgsT<double> &);
-template hipError_t launch_block_update<float>(hipStream_t, const BlockArgsT<float> &);
+template hipError_t launch_block_update<double>(hipStream_t, const BlockArgsT<double> &, int);
+template hipError_t launch_block_update<float>(hipStream_t, const BlockArgsT<float> &, int);
 template hipError_t launch_colnorm_pos<double>(hipStream_t, const double *, int, const int *, double *, int);
 template hipError_t launch_colnorm_pos<float>(hipStream_t, const float *, int, const int *, double *, int);
 

@@ -318,6 +318,17 @@ struct BlockArgsT {
     int4 *S_out;             // state of the next step (written by the update kernel)
     int ordering, step;      // step: outer step index inside the sweep
     int inner_sweeps = 0;    // 0: block-oriented; k > 0: full-block, at most k inner sweeps per pivot block
+    // Update kernel: blockIdx.y + tile0 is the tile (G tiles first, then V's).
+    int tile0 = 0;
+    // Inner kernels of a single problem: vprev_wgs extra workgroups apply the
+    // previous outer step's W (W_prev, active_prev, its outer pairs from S_prev
+    // or step_prev) to V.
+    int vprev_wgs = 0;
+    int vrows = 0;           // rows of V per V-update workgroup
+    T *W_prev = nullptr;
+    unsigned long long *active_prev = nullptr;
+    const int4 *S_prev = nullptr;
+    int step_prev = 0;
     T *partial;
     int splits, rows_per_split;
     T *W;
@@ -345,8 +356,14 @@ template <typename T>
 hipError_t launch_block_gram(hipStream_t st, const BlockArgsT<T> &a);
 template <typename T>
 hipError_t launch_block_inner(hipStream_t st, const BlockArgsT<T> &a);
+// Which tiles an update launch covers.
+enum { UPD_BOTH = 0, UPD_G = 1, UPD_V = 2 };
 template <typename T>
-hipError_t launch_block_update(hipStream_t st, const BlockArgsT<T> &a);
+hipError_t launch_block_update(hipStream_t st, const BlockArgsT<T> &a, int which = UPD_BOTH);
+// Rows per workgroup and workgroups that the V update of one outer step takes
+// inside an inner launch (cus: compute units of the device).
+int v_update_role_rows(int pairs, int ldg, int cus);
+int v_update_role_wgs(int pairs, int ldg, int vrows);
 template <typename T>
 hipError_t launch_colnorm_pos(hipStream_t st, const T *G, int ldg, const int *rho, double *d, int r);
 hipError_t launch_block_trace(hipStream_t st, int ordering, int r, int b, int step, int4 *S, int *out,
