@@ -110,7 +110,7 @@ Layout make_layout(int n, int r, int ldg, bool want_v, int pairs, int splits, in
     L.off_d = take(sizeof(double) * r);
     L.off_rho = take(sizeof(int) * r);
     L.off_dtmp = take(sizeof(double) * r);
-    L.off_rtmp = take(sizeof(int) * r);
+    L.off_rtmp = take(sizeof(int) * 2 * (size_t)r);  // sort: moved rho, then ranks
     L.off_S = take(sizeof(int4) * slots);
     L.off_C = take(sizeof(int) * slots);
     L.off_nrot = take(sizeof(unsigned int) * slots);

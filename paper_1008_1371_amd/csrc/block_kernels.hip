@@ -265,7 +265,7 @@ __global__ __launch_bounds__(1024) void block_inner_circle_kernel(BlockArgsT<T> 
     // vector loads), then every entry (x, y) taken from (min, max)
     {
         typedef T v4 __attribute__((ext_vector_type(4)));
-        constexpr int kChunk = 8;
+        constexpr int kChunk = sizeof(T) == 4 ? 16 : 8;
         const int x = tid >> 4, y0 = (tid & 15) * 4;
         if ((y0 >> 4) >= (x >> 4)) {
             const T *P = a.partial + (size_t)k * a.splits * (kB2 * kB2) + x * kB2 + y0;
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
     // vector loads; only the upper-triangular 16 x 16 tiles hold data.
     {
         typedef T v4 __attribute__((ext_vector_type(4)));
-        constexpr int kChunk = 8;
+        constexpr int kChunk = sizeof(T) == 4 ? 16 : 8;
         const int x = tid >> 4, y0 = (tid & 15) * 4;
         if ((y0 >> 4) >= (x >> 4)) {
             const T *P = a.partial + (size_t)k * a.splits * (kB2 * kB2) + x * kB2 + y0;

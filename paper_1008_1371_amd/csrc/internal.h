@@ -36,7 +36,7 @@ struct Workspace {
     double *d = nullptr;      // r: kept diagonal, by position
     int *rho = nullptr;       // r: physical column at each position
     double *dtmp = nullptr;   // r: sort scratch
-    int *rtmp = nullptr;      // r: sort scratch
+    int *rtmp = nullptr;      // 2r: sort scratch (moved rho, ranks)
     int4 *S = nullptr;        // r/2: modified modulus stepper state per slot (ip, jp, iblk, jblk)
     int *C = nullptr;         // r/2: per-slot convergence code of the current sweep (eq. 4.2)
     unsigned int *nrot = nullptr;   // r/2: per-slot rotations in the current sweep

@@ -185,45 +185,56 @@ __global__ __launch_bounds__(WG) void pair_step_kernel(StepArgs a)
 // smaller positions.  Keys are staged through LDS tiles.
 // ---------------------------------------------------------------------------
 constexpr int kSortTile = 2048;
+// Stable diagonal sort (Alg. 4.1): the destination of position q is the
+// number of positions of its sign segment that come before it (larger d in
+// [0, p), smaller d in [p, r); equal keys by position).  The count runs over a
+// 2-D grid of (256 positions) x (256 keys) tiles, each tile adding its exact
+// integer count into rank[q]; then every position moves to its rank.
 constexpr int kSortWG = 256;
+constexpr int kRankTile = 256;
 
-// Ranks of positions [blockIdx.x * 256, +256): every workgroup scans the keys of
-// the whole order through LDS tiles and scatters its positions' (d, rho) to
-// their ranks in (dtmp, rtmp).
-__global__ __launch_bounds__(kSortWG) void sort_rank_kernel(const double *__restrict__ d,
-                                                            const int *__restrict__ rho,
-                                                            double *__restrict__ dtmp,
-                                                            int *__restrict__ rtmp, int r, int p)
+__global__ __launch_bounds__(kSortWG) void sort_count_kernel(const double *__restrict__ d, int *__restrict__ rank,
+                                                             int r, int p)
 {
-    __shared__ double tile[kSortTile];
-    const int q = blockIdx.x * kSortWG + threadIdx.x;
-    const bool valid = q < r;
-    const double kq = valid ? d[q] : 0.0;
+    __shared__ double tile[kRankTile];
+    const int b0 = blockIdx.x * kSortWG, b1 = min(r, b0 + kSortWG);
+    const int kb = blockIdx.y * kRankTile, ke = min(r, kb + kRankTile);
+    // the keys of this workgroup's positions' segments
+    const int need_lo = b0 < p ? 0 : p, need_hi = b1 - 1 < p ? p : r;
+    if (ke <= need_lo || kb >= need_hi) return;
+    for (int u = threadIdx.x; u < ke - kb; u += kSortWG) tile[u] = d[kb + u];
+    __syncthreads();
+    const int q = b0 + threadIdx.x;
+    if (q >= r) return;
+    const double kq = d[q];
     const bool pos = q < p;
     const int lo = pos ? 0 : p, hi = pos ? p : r;
-    // positions of this workgroup span [b0, b1); only tiles meeting a segment they use are read
-    const int b0 = blockIdx.x * kSortWG, b1 = min(r, b0 + kSortWG);
-    const int need_lo = b0 < p ? 0 : p, need_hi = b1 - 1 < p ? p : r;
+    const int u0 = max(lo, kb) - kb, u1 = min(hi, ke) - kb;
     int cnt = 0;
-    for (int base = need_lo; base < need_hi; base += kSortTile) {
-        const int len = min(kSortTile, need_hi - base);
-        __syncthreads();
-        for (int u = threadIdx.x; u < len; u += kSortWG) tile[u] = d[base + u];
-        __syncthreads();
-        if (valid) {
-            const int u0 = max(lo, base) - base, u1 = min(hi, base + len) - base;
-            for (int u = u0; u < u1; ++u) {
-                const double kv = tile[u];
-                const bool before = pos ? (kv > kq) : (kv < kq);
-                cnt += (before || (kv == kq && base + u < q)) ? 1 : 0;
-            }
-        }
+#pragma unroll 8
+    for (int u = u0; u < u1; ++u) {
+        const double kv = tile[u];
+        const bool before = pos ? (kv > kq) : (kv < kq);
+        cnt += (before || (kv == kq && kb + u < q)) ? 1 : 0;
     }
-    if (valid) {
-        const int dst = lo + cnt;
-        dtmp[dst] = kq;
-        rtmp[dst] = rho[q];
-    }
+    if (cnt) atomicAdd(&rank[q], cnt);
+}
+
+__global__ __launch_bounds__(256) void sort_scatter_kernel(const double *__restrict__ d, const int *__restrict__ rho,
+                                                           int *__restrict__ rank, double *__restrict__ dtmp,
+                                                           int *__restrict__ rtmp, int r, int p)
+{
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= r) return;
+    const int dst = (q < p ? 0 : p) + rank[q];
+    dtmp[dst] = d[q];
+    rtmp[dst] = rho[q];
+}
+
+__global__ __launch_bounds__(256) void sort_zero_kernel(int *__restrict__ rank, int r)
+{
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q < r) rank[q] = 0;
 }
 
 __global__ __launch_bounds__(256) void sort_copy_kernel(double *__restrict__ d, int *__restrict__ rho,
@@ -474,9 +485,17 @@ hipError_t launch_pair_step(hipStream_t st, const StepArgs &a)
 
 hipError_t launch_sort(hipStream_t st, double *d, int *rho, double *dtmp, int *rtmp, int r, int p)
 {
+    // rtmp holds 2r ints: the moved rho, then the ranks
+    int *rank = rtmp + r;
     const int blocks = (r + kSortWG - 1) / kSortWG;
-    sort_rank_kernel<<<blocks, kSortWG, 0, st>>>(d, rho, dtmp, rtmp, r, p);
+    sort_zero_kernel<<<blocks, 256, 0, st>>>(rank, r);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    sort_count_kernel<<<dim3(blocks, (r + kRankTile - 1) / kRankTile), kSortWG, 0, st>>>(d, rank, r, p);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    sort_scatter_kernel<<<blocks, 256, 0, st>>>(d, rho, rank, dtmp, rtmp, r, p);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     sort_copy_kernel<<<blocks, 256, 0, st>>>(d, rho, dtmp, rtmp, r);
     return hipGetLastError();
