@@ -118,101 +118,88 @@ __device__ void v_update_role(const BlockArgsT<T> &a, int role);
 // ---------------------------------------------------------------------------
 // The Gram matrix is symmetric: only the 10 upper-triangular 16 x 16 tiles
 // (xt <= yt) of the 4 x 4 tiling are formed; readers take entry
-// (min(x, y), max(x, y)).  For a 4-row slice the MFMA operands of column tile
-// t are the same register for the A and the B side (A(i, k) in lane i + 16k,
-// B(k, j) in lane j + 16k, both G(row k, column 16t + lane % 16)), so a wave
-// loads the 4 tile operands once and issues all 10 products.  Each wave owns
-// every fourth 16-row sub-chunk of the split: it reads the 64 columns of its
-// rows with coalesced loads (lane = row within the sub-chunk), stages them in
-// its own LDS area (no block barrier in the main loop), prefetches the next
-// sub-chunk into registers and accumulates all 10 tiles.  The four waves'
-// tiles are summed in wave order at the end.
+// (min(x, y), max(x, y)).  An MFMA slice contracts 4 rows; operand A(i, k)
+// sits in lane i + 16k, operand B(k, j) in lane j + 16k, so with lane
+// (i, k) holding G(row_k, column 16t + i) the same register is the A operand
+// of column tile t and the B operand of tile t, and a wave issues all 10
+// products from its 4 tile registers.  The rows of a slice need not be
+// consecutive: lane (i, k) loads 16 consecutive bytes of column 16t + i
+// (V = 16 / sizeof(T) rows) at row offset V k, and element e of that load
+// serves slice e.  One load per tile (FP32) or two (FP64, rows + 4V) make a
+// chunk of 16 rows; lanes of one load instruction read 64 contiguous bytes
+// per column.  No LDS staging: the loads are the MFMA operands.  Wave w
+// takes every fourth chunk of the split; the four waves' tiles are summed in
+// wave order at the end.
 constexpr int kGramTiles = 10;
 __constant__ int kGramTX[kGramTiles] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
 __constant__ int kGramTY[kGramTiles] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
 
 template <typename T>
-struct GramLd {
-    // LDS row stride of a staged 16 x 64 sub-chunk (elements), chosen so that
-    // the 16 rows written by one load instruction fall into distinct banks
-    static constexpr int value = sizeof(T) == 8 ? kB2 + 2 : kB2 + 4;
-};
-
-template <typename T>
 __global__ __launch_bounds__(256) void block_gram_kernel(BlockArgsT<T> a)
 {
-    constexpr int kLdw = GramLd<T>::value;
-    constexpr int kSub = 16 * kLdw;  // one wave's staging area
-    __shared__ T Xs[4 * kSub];
-    __shared__ int cols[kB2];
+    constexpr int kV = 16 / (int)sizeof(T);  // rows per 16-byte load
+    // loads per tile and chunk: FP32 one (16 rows), FP64 two (8 rows each)
+    constexpr int NH = sizeof(T) == 4 ? 1 : 2;
+    constexpr int kRC = 4 * NH * kV;  // rows per chunk
+    typedef T vec __attribute__((ext_vector_type(kV)));
+    constexpr int kHalf = kGramTiles / 2;
+    __shared__ T red[3 * kHalf * 256];
     if (!bind_problem(a)) return;
     const int k = blockIdx.x, split = blockIdx.y;
     const int2 IJ = outer_pair(a, k);
-    if (threadIdx.x < kB2) cols[threadIdx.x] = a.rho[local_pos(threadIdx.x, IJ.x, IJ.y)];
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int row_begin = split * a.rows_per_split;
     const int row_end = min(a.ldg, row_begin + a.rows_per_split);
-    const int nsub = (row_end - row_begin) / 16;
-    // load e of a sub-chunk: column 4e + lane / 16, row lane % 16, as 32-bit
-    // byte offsets from the uniform base (r, ldg <= 16448: below 2^32 bytes)
+    const int nchunk = (row_end - row_begin) / kRC;
+    // byte offsets of this lane's first row in its 4 columns, 32-bit from the
+    // uniform base (r, ldg <= 16448: below 2^32 bytes)
     const char *__restrict__ G = reinterpret_cast<const char *>(a.G);
-    unsigned off[16];
+    unsigned off[4];
 #pragma unroll
-    for (int e = 0; e < 16; ++e)
-        off[e] = ((unsigned)cols[4 * e + lk] * (unsigned)a.ldg + (unsigned)(row_begin + lr)) * (unsigned)sizeof(T);
-    auto load = [&](int sub, T *v) {
-        const unsigned rb = (unsigned)(sub * 16) * (unsigned)sizeof(T);
-#pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = *reinterpret_cast<const T *>(G + (off[e] + rb));
-    };
-    T *X = Xs + wave * kSub;
+    for (int t = 0; t < 4; ++t)
+        off[t] = ((unsigned)a.rho[local_pos(16 * t + lr, IJ.x, IJ.y)] * (unsigned)a.ldg +
+                  (unsigned)(row_begin + kV * lk)) * (unsigned)sizeof(T);
     typename MF<T>::acc acc[kGramTiles];
 #pragma unroll
     for (int q = 0; q < kGramTiles; ++q) acc[q] = MF<T>::zero();
-    T pre[16];
-    if (wave < nsub) load(wave, pre);
-    for (int sub = wave; sub < nsub; sub += 4) {
+    // no prefetch: the registers go to occupancy instead (measured faster)
+    for (int c = wave; c < nchunk; c += 4) {
+        vec cur[4][NH];
+        const unsigned rb = (unsigned)(c * kRC) * (unsigned)sizeof(T);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) X[lr * kLdw + 4 * e + lk] = pre[e];
-        // next sub-chunk (the last one re-reads its own rows, from cache)
-        load(sub + 4 < nsub ? sub + 4 : sub, pre);
-        // the staged rows are read by other lanes of this wave only
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            T x[4];
+            for (int h = 0; h < NH; ++h)
+                cur[t][h] = *reinterpret_cast<const vec *>(G + (off[t] + rb + (unsigned)(h * 4 * kV) * sizeof(T)));
 #pragma unroll
-            for (int t = 0; t < 4; ++t) x[t] = X[(kk * 4 + lk) * kLdw + t * 16 + lr];
-            acc[0] = MF<T>::mma(x[0], x[0], acc[0]);
-            acc[1] = MF<T>::mma(x[0], x[1], acc[1]);
-            acc[2] = MF<T>::mma(x[0], x[2], acc[2]);
-            acc[3] = MF<T>::mma(x[0], x[3], acc[3]);
-            acc[4] = MF<T>::mma(x[1], x[1], acc[4]);
-            acc[5] = MF<T>::mma(x[1], x[2], acc[5]);
-            acc[6] = MF<T>::mma(x[1], x[3], acc[6]);
-            acc[7] = MF<T>::mma(x[2], x[2], acc[7]);
-            acc[8] = MF<T>::mma(x[2], x[3], acc[8]);
-            acc[9] = MF<T>::mma(x[3], x[3], acc[9]);
-        }
-        __builtin_amdgcn_wave_barrier();
+        for (int h = 0; h < NH; ++h)
+#pragma unroll
+            for (int e = 0; e < kV; ++e) {
+                const T x0 = cur[0][h][e], x1 = cur[1][h][e], x2 = cur[2][h][e], x3 = cur[3][h][e];
+                acc[0] = MF<T>::mma(x0, x0, acc[0]);
+                acc[1] = MF<T>::mma(x0, x1, acc[1]);
+                acc[2] = MF<T>::mma(x0, x2, acc[2]);
+                acc[3] = MF<T>::mma(x0, x3, acc[3]);
+                acc[4] = MF<T>::mma(x1, x1, acc[4]);
+                acc[5] = MF<T>::mma(x1, x2, acc[5]);
+                acc[6] = MF<T>::mma(x1, x3, acc[6]);
+                acc[7] = MF<T>::mma(x2, x2, acc[7]);
+                acc[8] = MF<T>::mma(x2, x3, acc[8]);
+                acc[9] = MF<T>::mma(x3, x3, acc[9]);
+            }
     }
-    // sum over the waves in wave order, five tiles at a time through the
-    // staging area (waves 1..3 deposit, wave 0 adds and stores)
+    // sum over the waves in wave order, five tiles at a time (waves 1..3
+    // deposit, wave 0 adds and stores)
     T *out = a.partial + ((size_t)k * a.splits + split) * (kB2 * kB2);
-    constexpr int kHalf = kGramTiles / 2;
-    static_assert(3 * kHalf * 256 <= 4 * kSub, "reduction area");
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        __syncthreads();
+        if (h) __syncthreads();
         if (wave > 0) {
 #pragma unroll
             for (int j = 0; j < kHalf; ++j)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) Xs[((wave - 1) * kHalf + j) * 256 + v * 64 + lane] = acc[h * kHalf + j][v];
+                for (int v = 0; v < 4; ++v) red[((wave - 1) * kHalf + j) * 256 + v * 64 + lane] = acc[h * kHalf + j][v];
         }
         __syncthreads();
         if (wave == 0) {
@@ -223,7 +210,7 @@ __global__ __launch_bounds__(256) void block_gram_kernel(BlockArgsT<T> a)
                 for (int v = 0; v < 4; ++v) {
                     T sum = acc[q][v];
 #pragma unroll
-                    for (int w = 0; w < 3; ++w) sum += Xs[(w * kHalf + j) * 256 + v * 64 + lane];
+                    for (int w = 0; w < 3; ++w) sum += red[(w * kHalf + j) * 256 + v * 64 + lane];
                     const int x = kGramTX[q] * 16 + MF<T>::row(lane, v);
                     const int y = kGramTY[q] * 16 + lr;
                     out[x * kB2 + y] = sum;
