@@ -91,8 +91,11 @@ def parse():
     return ap.parse_args()
 
 
-def accuracy(G, p, R):
-    """Invariants of a solve, in FP64 on the GPU (torch matmuls)."""
+def accuracy(G, p, R, lam=None):
+    """Invariants of a solve, in FP64 on the GPU (torch matmuls).  With the
+    prescribed spectrum lam of an eigen workload, also the relative errors of
+    the computed eigenvalues sigma^2 j and d(U) = ||I - U^T U||_F (Sec. 5)."""
+    import numpy as np
     import torch
     n = G.shape[0]
     U, V, s = R["U"], R["V"], R["sigma"]
@@ -103,6 +106,14 @@ def accuracy(G, p, R):
     # from the returned U they may exceed it by rounding (the tests allow 2 tol)
     out = {"max_offdiag_UtU": (UtU - torch.diag(torch.diagonal(UtU))).abs().max().item(),
            "tol": 1e-15 * n, "bound": 2e-15 * n}
+    if lam is not None:
+        got = np.sort((s * s * j).cpu().numpy())
+        want = np.sort(lam)
+        rel = np.abs(got - want) / np.abs(want)
+        out["eig_rel_max"] = float(rel.max())
+        out["eig_rel_mean"] = float(rel.mean())
+        out["eig_rel_bound"] = 20 * n * float(np.finfo(np.float64).eps / 2)
+        out["dU"] = torch.linalg.matrix_norm(torch.eye(n, dtype=torch.float64, device=G.device) - UtU).item()
     if V is not None:
         VtJV = V.t() @ (V * j[:, None])
         vn = torch.linalg.matrix_norm(V, ord=2).item() ** 2
@@ -233,6 +244,8 @@ def main():
     H.lib()  # fails loudly if the HIP library is missing
     G_np, p = W.workload(args.workload)
     n = G_np.shape[0]
+    # the prescribed spectrum of an eigen workload (cached by the generator)
+    lam = W.eigen(n)[2] if args.workload.startswith("eigen") else None
     dev = torch.device("cuda:0")
     G = torch.from_numpy(np.asfortranarray(G_np)).to(dev)
     ctx = H.Context(0)
@@ -263,7 +276,7 @@ def main():
     modes = ["fp64", "mixed"] if args.mode == "both" else [args.mode]
     for mode in modes:
         ms, infos, R = timed(H, ctx, G, p, params(mode), out, args.steps, args.warmup, check)
-        acc = None if args.no_accuracy else accuracy(G, p, R)
+        acc = None if args.no_accuracy else accuracy(G, p, R, lam)
         runs[mode] = (ms, infos, acc)
     head = "mixed" if "mixed" in runs else modes[0]
     ms, infos, acc = runs[head]

@@ -41,8 +41,25 @@ def _compile(src: str) -> str:
     return obj
 
 
+GEN_SRC = os.path.join(CSRC, "gen_indefinite.c")
+GEN_LIB = os.path.join(HERE, "libhsvd_gen.so")
+
+
+def build_gen() -> str:
+    """Host library of the extended-precision test-matrix generator (gcc,
+    OpenMP; x87 long double)."""
+    tmp = GEN_LIB + ".tmp"
+    cmd = [os.environ.get("CC", "gcc"), "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", GEN_SRC, "-o", tmp, "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"gcc failed for gen_indefinite.c:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, GEN_LIB)
+    return GEN_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
+    build_gen()
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"

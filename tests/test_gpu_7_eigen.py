@@ -1,0 +1,87 @@
+"""The paper's kind of input (Sec. 5: symmetric indefinite M with a prescribed
+random spectrum, factor G from a complete-pivoting indefinite factorisation in
+extended precision) through the library (GPU): parity with the oracle, and
+the computed eigenvalues sigma^2 j against the prescribed spectrum."""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+from gpu_util import run_lib, say
+from parity import compare, ordering_spread, twin_spread
+from paper_1008_1371_amd import workloads as W
+from test_eigen_workload import EIG_REL, U64, _eig_errors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,algo", [(160, 1), (288, 2), (416, 2)])
+def test_eigen_parity_fp64(hsvd_ctx, n, algo):
+    """FP64 pairwise (algo 1) and block (algo 2) paths against the oracle's
+    same ordering, and the spectrum."""
+    G, p, lam = W.eigen(n)
+    block = 32 if algo == 2 else 0
+    spread, ref = twin_spread(G, p, block=block)
+    res = run_lib(hsvd_ctx, G, p, algo=algo)
+    assert res["status"] == 0, res["status"]
+    e = compare(res, ref, p)
+    rel = _eig_errors(res, p, lam)
+    say("eigen", n, "algo", algo, e, "twin", spread, "eig rel max/mean", rel.max(), rel.mean(),
+        "sweeps lib/orc", res["sweeps"], ref["sweeps"])
+    assert e["sigma_norm"] <= 1e-12
+    gate = max(1e-12, 10 * max(spread["U"], spread["V"]))
+    assert e["U"] <= gate and e["V"] <= gate, e
+    assert rel.max() <= EIG_REL * n * U64
+    pins.check_invariants(G, p, res, tol=ref["tol"])
+
+
+@pytest.mark.parametrize("n", [288, 544])
+def test_eigen_mixed(hsvd_ctx, n):
+    """Mixed precision: FP32 sweeps, then FP64 refinement; the eigenvalues
+    keep their relative accuracy."""
+    G, p, lam = W.eigen(n)
+    spread, ref = ordering_spread(G, p, block=32)
+    res = run_lib(hsvd_ctx, G, p, precision=1)
+    assert res["status"] == 0, res["status"]
+    e = compare(res, ref, p)
+    rel = _eig_errors(res, p, lam)
+    say("eigen mixed", n, e, "ordering spread", spread, "eig rel max", rel.max(),
+        "fp32/fp64 sweeps", res["info"]["sweeps_fp32"], res["info"]["sweeps"])
+    assert e["sigma_norm"] <= 1e-12
+    gate = max(1e-12, 10 * max(spread["U"], spread["V"]))
+    assert e["U"] <= gate and e["V"] <= gate, e
+    assert rel.max() <= EIG_REL * n * U64
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_eigen_1056_spectrum(hsvd_ctx, precision):
+    """Order 160 + 128 * 7 (the paper's orders are 160 + 128k), a = 20: the
+    spectrum check alone (no oracle run at this size), both precisions."""
+    n = 1056
+    G, p, lam = W.eigen(n)
+    res = run_lib(hsvd_ctx, G, p, algo=2, precision=precision)
+    assert res["status"] == 0, res["status"]
+    rel = _eig_errors(res, p, lam)
+    U = res["U"]
+    dU = np.linalg.norm(np.eye(n) - U.T @ U)
+    say("eigen1056 precision", precision, "eig rel max/mean", rel.max(), rel.mean(), "d(U)", dU,
+        "sweeps", res["info"]["sweeps_fp32"], res["info"]["sweeps"])
+    assert rel.max() <= EIG_REL * n * U64
+    pins.check_invariants(G, p, res, tol=1e-15 * n)
+
+
+def test_eigen_jsig_unordered(hsvd_ctx):
+    """The factor straight from the factorisation, signs in pivot order,
+    through hsvd_solve_j: same eigenvalues as the reordered solve."""
+    import torch
+
+    from paper_1008_1371_amd import hsvd as H
+    n = 160
+    G, jsig, lam, _ = W.indefinite(n)
+    R = H.hsvd_solve_j(hsvd_ctx, torch.from_numpy(np.array(G, order="F")).cuda(),
+                       torch.from_numpy(np.array(jsig)).cuda(), H.hsvd_default_params(algo=2))
+    got = np.sort(R["lam"].cpu().numpy())
+    rel = np.abs(got - np.sort(lam)) / np.abs(np.sort(lam))
+    say("eigen jsig", rel.max())
+    assert rel.max() <= EIG_REL * n * U64
