@@ -444,7 +444,11 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
 {
     // A_P staging at the start, the two LR / RL exchange buffers in the loop
     __shared__ double buf[kB2 * kLd];
-    __shared__ double4 prm[2][kB];  // (t, c, t or -t, rotated) of each slot
+    // per slot (t, c), c negated for an applied trigonometric rotation (whose
+    // h is -t; otherwise h = t): 16 bytes per read, the LDS reads being the
+    // bulk of an inner step
+    __shared__ double2 prm[2][kB];
+    __shared__ int rotf[2][kB];  // slot rotated (read by the diagonal blocks)
     if ((int)blockIdx.x >= a.nb / 2) {
         v_update_role(a, (int)blockIdx.x - a.nb / 2);
         return;
@@ -524,7 +528,6 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
             double t, c;
             const int bad = rotation_params_fast(pll, prr, plr, hyp, t, c);
             const bool skip = rel_orthogonal_sq(pll, prr, plr, a.tol, tol2);
-            double h = 0.0;
             int rot = 0;
             if (skip) {
                 ++nskip;
@@ -539,10 +542,10 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
                 ++nrot;
                 code |= rotation_code(t, a.tthresh);
                 maxt = fmax(maxt, fabs(t));
-                h = hyp < 0 ? -t : t;
                 tmask |= (1ull << s) | (1ull << (kB + ((s + u) & 31)));
             }
-            prm[pb][s] = make_double4(t, c, h, rot ? 1.0 : 0.0);
+            prm[pb][s] = make_double2(t, (rot && hyp < 0) ? -c : c);
+            rotf[pb][s] = rot;
         }
         __syncthreads();
         if (u > 0) {
@@ -550,11 +553,16 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
             LR = xlr[(pb ^ 1) * (kB * kB) + lr_cell];
             RL = xrl[(pb ^ 1) * (kB * kB) + rl_cell];
         }
+        // slots s1 and s2; W's column slot w2 is s1.  (t, c, h) with h = -t
+        // for a trigonometric rotation
+        const double2 r1 = prm[pb][s1], r2 = prm[pb][s2];
+        const double3 p1 = make_double3(r1.x, fabs(r1.y), r1.y < 0.0 ? -r1.x : r1.x);
+        const double3 p2 = make_double3(r2.x, fabs(r2.y), r2.y < 0.0 ? -r2.x : r2.x);
         // A block, rows by slot s1, columns by slot s2.  Columns first iff
         // s1 <= s2; otherwise the same column-then-row sequence runs on the
         // transposed block with the slots exchanged, which is the
         // row-then-column order on the block itself.
-        const double4 pa = prm[pb][cf ? s2 : s1], pq = prm[pb][cf ? s1 : s2];
+        const double3 pa = cf ? p2 : p1, pq = cf ? p1 : p2;
         {
             const double x01 = cf ? LR : RL, x10 = cf ? RL : LR;
             const double f00 = fma(pa.z, x01, LL) * pa.y, f01 = fma(pa.x, LL, x01) * pa.y;
@@ -566,7 +574,7 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
             LR = cf ? y01 : y10;
             RL = cf ? y10 : y01;
         }
-        if (diag && pa.w != 0.0) {
+        if (diag && rotf[pb][s1]) {
             LR = 0.0;
             RL = 0.0;
         }
@@ -584,7 +592,7 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
         }
         // W <- W R on columns (L_w2, R_w2), then the shift of its R half
         {
-            const double4 pw = prm[pb][w2];
+            const double3 pw = p1;
             const double a0 = fma(pw.z, W0R, W0L) * pw.y, b0 = fma(pw.x, W0L, W0R) * pw.y;
             const double a1 = fma(pw.z, W1R, W1L) * pw.y, b1 = fma(pw.x, W1L, W1R) * pw.y;
             W0L = a0;
