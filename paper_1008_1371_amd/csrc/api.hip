@@ -643,14 +643,29 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             fa.tol = tol32;
             fa.tthresh = sqrt(tol32) / 2.0;
             fa.inner_sweeps = prm.inner_sweeps;
-            double prev = 1.0;
+            double prev = 1.0, prev_frac = 1.0;
+            unsigned long long rot0 = 0, skip0 = 0;  // the counters start at zero with the solve
             int sw32 = 0;
             // Leave FP32 when the largest tangent of a sweep is at the FP32
             // resolution (<= 3e-4 ~ sqrt(eps32)), when it stagnates (falls by
-            // less than 4x once below 0.1), or when FP32 itself converged.
+            // less than 4x once below 0.1), when FP32 itself converged, or by
+            // the fraction f of the sweep's pair visits that rotated: f < 1/100
+            // (the tail of a geometric decline; the first FP64 sweep rotates
+            // nearly every pair again in any case), or f <= 1/3 while falling by
+            // less than a quarter per sweep (a slow decline: the remaining
+            // rotations are below what FP32 resolves and the FP64 sweeps redo
+            // them).
             auto done32 = [&](const SweepResult &sr) {
-                const bool stop = sr.maxt <= 3e-4 || (sr.code & 2) == 0 || (sr.maxt < 0.1 && sr.maxt > 0.25 * prev);
+                const unsigned long long rot = ctx->host_ctl->rot, skip = ctx->host_ctl->skip;
+                const double dr = (double)(rot - rot0), ds = (double)(skip - skip0);
+                const double frac = dr + ds > 0.0 ? dr / (dr + ds) : 0.0;
+                rot0 = rot;
+                skip0 = skip;
+                const bool stop = sr.maxt <= 3e-4 || (sr.code & 2) == 0 ||
+                                  (sr.maxt < 0.1 && sr.maxt > 0.25 * prev) || frac < 0.01 ||
+                                  (frac <= 1.0 / 3.0 && frac >= 0.75 * prev_frac);
                 prev = sr.maxt;
+                prev_frac = frac;
                 return stop;
             };
             status = block_sweeps<float>(ctx, w, fa, w.G32, pairs, steps_per_sweep, max_sweeps, prm.sort != 0, r,
