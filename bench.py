@@ -26,21 +26,26 @@ FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a
-# second run, WRITE_SIZE (KiB per dispatch, averaged over all launches of one
-# mixed colscaled4096 solve), each scaled by what the same counter reads for a
-# plain 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  The figures
-# hold only for the kernel source they were taken on: when block_kernels.hip
-# no longer has this SHA-256 the roofline reports traffic as null.
+# second run, WRITE_SIZE (KiB per dispatch, averaged over all launches of each
+# kernel class in one mixed colscaled4096 solve), each scaled by what the same
+# counter reads for a plain 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE
+# x 1.0).  The averages hold only for the sources they were taken on (the
+# kernels, and the host code that sets their launch shapes and the solve's
+# trajectory): when the SHA-256 over these files changes the roofline reports
+# traffic as null.
 MEASURED_TRAFFIC = {
     "workload": "colscaled4096",
     "mode": "mixed",
-    "source": "paper_1008_1371_amd/csrc/block_kernels.hip",
-    "sha256": "14c06639c0b7c6876053151c404fbfcfb0925bafafba8946bde00100a5d34334",
+    "sources": ["paper_1008_1371_amd/csrc/block_kernels.hip", "paper_1008_1371_amd/csrc/api.hip",
+                "paper_1008_1371_amd/csrc/internal.h"],
+    "sha256": "f9dd2faa89dba6c1b2f518b70843ea151c867f42a717d7ce58aabfb75379184b",
     "bytes_per_launch": {
-        "block_update_kernel<float>": (30584.6 * 2.0 + 61553.6) * 1024,
-        "block_gram_kernel<float>": (33002.6 * 2.0 + 10241.8) * 1024,
-        "block_update_kernel<double>": (73934.4 * 2.0 + 143138.0) * 1024,
-        "block_gram_kernel<double>": (66398.0 * 2.0 + 20480.0) * 1024,
+        "block_gram_kernel<float>": (33077.8 * 2.0 + 10240.9 * 1.0) * 1024,
+        "block_inner_kernel<float>": (25162.9 * 2.0 + 37289.3 * 1.0) * 1024,
+        "block_update_kernel<float>": (18740.0 * 2.0 + 36852.9 * 1.0) * 1024,
+        "block_gram_kernel<double>": (65612.4 * 2.0 + 20480.0 * 1.0) * 1024,
+        "block_inner_kernel<double>": (29578.3 * 2.0 + 37521.5 * 1.0) * 1024,
+        "block_update_kernel<double>": (18369.8 * 2.0 + 35548.2 * 1.0) * 1024,
     },
 }
 
@@ -53,12 +58,15 @@ def measured_traffic(kernel, workload, mode):
     t = MEASURED_TRAFFIC
     if workload != t["workload"] or mode != t["mode"] or kernel not in t["bytes_per_launch"]:
         return None
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), t["source"])
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
     try:
-        with open(path, "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
-                return None
+        for src in t["sources"]:
+            with open(os.path.join(root, src), "rb") as f:
+                h.update(f.read())
     except OSError:
+        return None
+    if h.hexdigest() != t["sha256"]:
         return None
     return t["bytes_per_launch"][kernel]
 
