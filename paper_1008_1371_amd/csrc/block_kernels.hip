@@ -933,15 +933,19 @@ hipError_t launch_block_gram(hipStream_t st, const BlockArgsT<T> &a)
     return hipGetLastError();
 }
 
-// Rows of V per role workgroup: the V update of one step spread over about
-// the CUs that the inner solves leave free (multiples of 256 rows, one
-// 16-row strip per wave at least).
+// Rows of V per role workgroup: the V update of one step spread over the CUs
+// that the inner solves leave free (as many tiles per pair as fit, but at
+// least 256 rows -- a 16-row strip per wave -- per tile), in whole 16-row
+// strips so that the tiles of a pair come out nearly equal (the launch waits
+// for the largest).
 int v_update_role_rows(int pairs, int ldg, int cus)
 {
     const int free_cus = cus > pairs ? cus - pairs : 1;
-    const long long total = (long long)pairs * ldg;
-    int rows = (int)((total + free_cus - 1) / free_cus);
-    rows = (rows + 255) / 256 * 256;
+    int tiles = free_cus / pairs;
+    if (tiles > ldg / 256) tiles = ldg / 256;
+    if (tiles < 1) tiles = 1;
+    int rows = (ldg + tiles - 1) / tiles;
+    rows = (rows + 15) / 16 * 16;
     return rows < ldg ? rows : ldg;
 }
 
