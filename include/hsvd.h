@@ -227,7 +227,10 @@ hsvd_status hsvd_block_trace(hsvd_ctx *ctx, int ordering, int r, int b, int step
 
 /* Device diagonal sort (Sec. 4, Sort_Diagonal): stable; positions [0, p) by
  * d decreasing, [p, r) by d increasing; rho travels with d.  In place on
- *   d (device, r doubles), rho (device, r ints).  r <= 16384.
+ *   d (device, r doubles), rho (device, r ints).  r <= 16384.  Keys are
+ *   compared in the IEEE-754 total order of their bit patterns: the numeric
+ *   order on the non-negative values the solver produces (it separates -0.0
+ *   from +0.0 and places NaN beyond +inf), and a permutation for any input.
  * Synchronises.  Errors: HSVD_E_INVAL. */
 hsvd_status hsvd_sort_diag(hsvd_ctx *ctx, int r, int p, double *d, int *rho);
 

@@ -70,10 +70,12 @@ __global__ __launch_bounds__(256) void batch_colnorm_kernel(BatchGroup g, int in
 }
 
 // Stable diagonal sort of each problem (positions [0, p) by d decreasing,
-// [p, r) increasing), one workgroup per problem (r <= 1024).  grid nprob
+// [p, r) increasing; keys compared by sort_key), one workgroup per problem
+// (r <= 1024).  grid nprob
 __global__ __launch_bounds__(1024) void batch_sort_kernel(BatchGroup g)
 {
-    __shared__ double key[1024];
+    __shared__ long long key[1024];
+    __shared__ double dv[1024];
     __shared__ int val[1024];
     const int z = blockIdx.x;
     if (g.done[z]) return;
@@ -82,21 +84,22 @@ __global__ __launch_bounds__(1024) void batch_sort_kernel(BatchGroup g)
     int *rho = g.rho + (size_t)z * r;
     const int q = threadIdx.x;
     if (q < r) {
-        key[q] = d[q];
+        dv[q] = d[q];
+        key[q] = sort_key(dv[q]);
         val[q] = rho[q];
     }
     __syncthreads();
     if (q < r) {
-        const double kq = key[q];
+        const long long kq = key[q];
         const bool pos = q < p;
         const int lo = pos ? 0 : p, hi = pos ? p : r;
         int cnt = 0;
         for (int u = lo; u < hi; ++u) {
-            const double kv = key[u];
+            const long long kv = key[u];
             const bool before = pos ? (kv > kq) : (kv < kq);
             cnt += (before || (kv == kq && u < q)) ? 1 : 0;
         }
-        d[lo + cnt] = kq;
+        d[lo + cnt] = dv[q];
         rho[lo + cnt] = val[q];
     }
 }

@@ -192,6 +192,17 @@ __device__ __forceinline__ bool rel_orthogonal_sq(double aii, double ajj, double
     return aij * aij < rhs;
 }
 
+// Sort key of a diagonal entry: the IEEE-754 total order of its bit pattern,
+// as a signed integer.  On the non-negative values of d (sums of squares,
+// never -0) it orders exactly as the values; on any input, NaN included, it
+// is a total order, so the ranks of the sort always form a permutation and
+// rho stays one.
+__device__ __forceinline__ long long sort_key(double x)
+{
+    const long long k = __double_as_longlong(x);
+    return k < 0 ? (k ^ 0x7fffffffffffffffLL) : k;
+}
+
 // Eq. (4.2) code of one applied rotation, to be OR-ed into the slot's code.
 __device__ __forceinline__ int rotation_code(double t, double tthresh)
 {

@@ -187,7 +187,8 @@ __global__ __launch_bounds__(WG) void pair_step_kernel(StepArgs a)
 constexpr int kSortTile = 2048;
 // Stable diagonal sort (Alg. 4.1): the destination of position q is the
 // number of positions of its sign segment that come before it (larger d in
-// [0, p), smaller d in [p, r); equal keys by position).  The count runs over a
+// [0, p), smaller d in [p, r); equal keys by position), keys compared by
+// sort_key.  The count runs over a
 // 2-D grid of (256 positions) x (256 keys) tiles, each tile adding its exact
 // integer count into rank[q]; then every position moves to its rank.
 constexpr int kSortWG = 256;
@@ -196,24 +197,24 @@ constexpr int kRankTile = 256;
 __global__ __launch_bounds__(kSortWG) void sort_count_kernel(const double *__restrict__ d, int *__restrict__ rank,
                                                              int r, int p)
 {
-    __shared__ double tile[kRankTile];
+    __shared__ long long tile[kRankTile];
     const int b0 = blockIdx.x * kSortWG, b1 = min(r, b0 + kSortWG);
     const int kb = blockIdx.y * kRankTile, ke = min(r, kb + kRankTile);
     // the keys of this workgroup's positions' segments
     const int need_lo = b0 < p ? 0 : p, need_hi = b1 - 1 < p ? p : r;
     if (ke <= need_lo || kb >= need_hi) return;
-    for (int u = threadIdx.x; u < ke - kb; u += kSortWG) tile[u] = d[kb + u];
+    for (int u = threadIdx.x; u < ke - kb; u += kSortWG) tile[u] = sort_key(d[kb + u]);
     __syncthreads();
     const int q = b0 + threadIdx.x;
     if (q >= r) return;
-    const double kq = d[q];
+    const long long kq = sort_key(d[q]);
     const bool pos = q < p;
     const int lo = pos ? 0 : p, hi = pos ? p : r;
     const int u0 = max(lo, kb) - kb, u1 = min(hi, ke) - kb;
     int cnt = 0;
 #pragma unroll 8
     for (int u = u0; u < u1; ++u) {
-        const double kv = tile[u];
+        const long long kv = tile[u];
         const bool before = pos ? (kv > kq) : (kv < kq);
         cnt += (before || (kv == kq && kb + u < q)) ? 1 : 0;
     }

@@ -108,3 +108,36 @@ def test_sort_bit_exact(hsvd_ctx, r, p):
     rr = torch.from_numpy(rho.copy()).cuda()
     H.hsvd_sort_diag(hsvd_ctx, dd, rr, p)
     assert np.array_equal(dd.cpu().numpy(), wd) and np.array_equal(rr.cpu().numpy(), wr)
+
+
+def _total_order_key(d):
+    k = d.view(np.int64)
+    return np.where(k < 0, k ^ np.int64(0x7FFFFFFFFFFFFFFF), k)
+
+
+@pytest.mark.parametrize("r,p", [(64, 20), (1000, 400), (5000, 2500)])
+def test_sort_non_finite_keys_give_a_permutation(hsvd_ctx, r, p):
+    """NaN, infinities and signed zeros (which the solver never produces):
+    the sort still returns a permutation of rho, in the IEEE total order of
+    the keys, stable."""
+    import torch
+
+    from paper_1008_1371_amd import hsvd as H
+    g = np.random.Generator(np.random.PCG64(7 * r + p))
+    d = g.uniform(-4, 4, r)
+    specials = np.array([np.nan, -np.nan, np.inf, -np.inf, 0.0, -0.0, 1.0, 1.0])
+    d[g.integers(0, r, r // 4)] = g.choice(specials, r // 4)
+    rho = g.permutation(r).astype(np.int32)
+    say("sort non-finite", r, p)
+    dd = torch.from_numpy(d.copy()).cuda()
+    rr = torch.from_numpy(rho.copy()).cuda()
+    H.hsvd_sort_diag(hsvd_ctx, dd, rr, p)
+    got_d, got_r = dd.cpu().numpy(), rr.cpu().numpy()
+    assert np.array_equal(np.sort(got_r), np.sort(rho))
+    key = _total_order_key(d)
+    idx = np.arange(r)
+    o1 = np.lexsort((idx[:p], ~key[:p]))  # decreasing, ties by position
+    o2 = p + np.lexsort((idx[p:], key[p:]))  # increasing
+    order = np.concatenate([o1, o2])
+    assert np.array_equal(got_r, rho[order])
+    assert np.array_equal(got_d.view(np.int64), d[order].view(np.int64))
