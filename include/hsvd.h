@@ -56,8 +56,10 @@ typedef struct {
     int max_sweeps;  /* <= 0: 100                                                        */
     double tol;      /* threshold of the relative orthogonality test (eq. 2.3); <= 0: 1e-15 n */
     double t_thresh; /* T of eq. (4.2); <= 0: sqrt(tol) / 2 (Sec. 2)                     */
-    int graph;       /* hsvd_solve_batched: 1 = capture one sweep of a group as a HIP
-                        graph and replay it (no per-kernel timing in hsvd_info)        */
+    int graph;       /* 1 = capture one sweep's launches as a HIP graph and replay it
+                        every sweep: the step launches of the pairwise path (timed per
+                        sweep as before), and a whole sweep of a batched group (no
+                        per-kernel timing in hsvd_info then); 0 = stream launches     */
     int inner_sweeps; /* block path.  0: block-oriented method (Sec. 5) -- each outer step
                         annihilates the pivot block's off-diagonal entries once (all pairs
                         of the 2b columns in the first outer step of a sweep, the cross

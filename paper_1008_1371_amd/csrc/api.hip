@@ -296,6 +296,48 @@ struct SweepResult {
 // mean of its timed ones.
 constexpr int kTimeEvery = 8;
 
+// Capture of one sweep's launches on the context's capture stream (default
+// priority, non-blocking) and its replay.  begin() joins the capture stream
+// to the caller's stream and starts capturing; end() instantiates.  The
+// destructor frees the graph and joins the caller's stream back to the
+// capture stream, on every exit path.
+struct SweepGraph {
+    hsvd_ctx *ctx;
+    hipStream_t st;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool used = false;
+    SweepGraph(hsvd_ctx *c, hipStream_t s) : ctx(c), st(s) {}
+    hipError_t begin(hipStream_t &q)
+    {
+        hipError_t e;
+        if (!ctx->cap && (e = hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking)) != hipSuccess) return e;
+        if (!ctx->join && (e = hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming)) != hipSuccess) return e;
+        q = ctx->cap;
+        used = true;
+        if ((e = hipEventRecord(ctx->join, st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(q, ctx->join, 0)) != hipSuccess) return e;
+        return hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal);
+    }
+    hipError_t end(hipStream_t q)
+    {
+        hipError_t e = hipStreamEndCapture(q, &graph);
+        if (e != hipSuccess) return e;
+        return hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    }
+    void abort(hipStream_t q)
+    {
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(q, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+    }
+    ~SweepGraph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (used && hipEventRecord(ctx->join, ctx->cap) == hipSuccess) (void)hipStreamWaitEvent(st, ctx->join, 0);
+    }
+};
+
 // Runs block sweeps of storage type T until `done(sweep_result)` says so or
 // max_sweeps is reached.  Kernel times go to kms[kbase + 0..2] (Gram, inner,
 // update), the number of timed launches to ktimed.  Returns HSVD_OK,
@@ -584,20 +626,45 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
         a.ordering = prm.ordering;
         a.tol = tol;
         a.tthresh = tthresh;
-        for (int sw = 0; sw < max_sweeps; ++sw) {
-            HSVD_TRY(hipEventRecord(ev[2], st));
+        // The r (or r - 1) dependent step launches of a sweep are captured
+        // once as a HIP graph and replayed every sweep (the stepper state
+        // lives in device memory and every launch's arguments repeat from
+        // sweep to sweep); a step moves only a few MB at moderate n, so the
+        // per-launch gap of stream launches is a large share of it.  The
+        // sweep runs on the context's capture stream, joined to the caller's
+        // stream before and after.
+        SweepGraph sg(ctx, st);
+        hipStream_t q = st;
+        if (prm.graph) {
+            HSVD_TRY(sg.begin(q));
             for (int k = 0; k < steps_per_sweep; ++k) {
                 a.step = k;
-                HSVD_TRY(launch_pair_step(st, a));
+                const hipError_t le = launch_pair_step(q, a);
+                if (le != hipSuccess) {
+                    sg.abort(q);
+                    return HSVD_E_DEVICE;
+                }
             }
-            HSVD_TRY(hipEventRecord(ev[3], st));
+            HSVD_TRY(sg.end(q));
+        }
+        for (int sw = 0; sw < max_sweeps; ++sw) {
+            HSVD_TRY(hipEventRecord(ev[2], q));
+            if (prm.graph) {
+                HSVD_TRY(hipGraphLaunch(sg.exec, q));
+            } else {
+                for (int k = 0; k < steps_per_sweep; ++k) {
+                    a.step = k;
+                    HSVD_TRY(launch_pair_step(q, a));
+                }
+            }
+            HSVD_TRY(hipEventRecord(ev[3], q));
             klaunch[HSVD_K_PAIR_STEP] += steps_per_sweep;
             ktimed[HSVD_K_PAIR_STEP] += steps_per_sweep;
             steps += steps_per_sweep;
-            if (prm.sort) HSVD_TRY(launch_sort(st, w.d, w.rho, w.dtmp, w.rtmp, r, p));
-            HSVD_TRY(launch_sweep_reduce(st, w, r / 2));
-            HSVD_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-            HSVD_TRY(hipStreamSynchronize(st));
+            if (prm.sort) HSVD_TRY(launch_sort(q, w.d, w.rho, w.dtmp, w.rtmp, r, p));
+            HSVD_TRY(launch_sweep_reduce(q, w, r / 2));
+            HSVD_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, q));
+            HSVD_TRY(hipStreamSynchronize(q));
             float ms = 0.f;
             HSVD_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
             kms[HSVD_K_PAIR_STEP] += ms;

@@ -120,3 +120,19 @@ def test_signature_in_any_order(hsvd_ctx, n, algo):
     assert np.linalg.norm(Vj.T @ J @ Vj - J) / np.linalg.norm(Vj, 2) ** 2 <= 1e-11
     assert np.linalg.norm(G @ Vj - Uj * sj) / np.linalg.norm(G) <= 1e-13 * np.linalg.norm(Vj, 2)
     assert ((Rj["lam"].cpu().numpy() > 0) == (j > 0)).all()
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_pairwise_graph_replay_matches_eager(hsvd_ctx, ordering):
+    """Each sweep replays one captured graph of the step launches, with the
+    sort, reduction and read-back running eagerly in between: after every
+    sweep (max_sweeps = 1 .. 4 returns that iterate) the state is bit-identical
+    to launching the steps one by one."""
+    G = W.graded(256, 1e6, seed1=71, seed2=72)
+    for k in (1, 2, 3, 4):
+        eager = run_lib(hsvd_ctx, G, 160, algo=1, ordering=ordering, graph=0, max_sweeps=k)
+        graph = run_lib(hsvd_ctx, G, 160, algo=1, ordering=ordering, graph=1, max_sweeps=k)
+        say("graph replay", ordering, k, eager["status"], graph["status"])
+        assert eager["status"] == graph["status"]
+        for key in ("sigma", "U", "V", "lam", "perm"):
+            assert np.array_equal(eager[key], graph[key]), (k, key)
