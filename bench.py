@@ -131,6 +131,33 @@ def accuracy(G, p, R, lam=None):
     return out
 
 
+def canonical_diff(ref, got, p):
+    """Relative differences of `got` from `ref` (sigma, U, V; several results
+    are correct): within each J class (physical columns [0, p) and [p, n))
+    the columns are ordered by sigma descending, then each column pair of
+    `got` is sign-aligned to `ref` at the row where ref's u is largest."""
+    import torch
+
+    def order(s):
+        idx = torch.arange(s.numel(), device=s.device)
+        return torch.cat([idx[:p][torch.argsort(-s[:p], stable=True)],
+                          idx[p:][torch.argsort(-s[p:], stable=True)]])
+    o0, o1 = order(ref["sigma"]), order(got["sigma"])
+    s0, s1 = ref["sigma"][o0], got["sigma"][o1]
+    U0, U1 = ref["U"][:, o0], got["U"][:, o1]
+    cols = torch.arange(U0.shape[1], device=U0.device)
+    rows = U0.abs().argmax(dim=0)
+    flip = torch.sign(U0[rows, cols]) * torch.sign(U1[rows, cols])
+    flip[flip == 0] = 1.0
+    out = {"sigma_norm": (torch.linalg.vector_norm(s1 - s0) / torch.linalg.vector_norm(s0)).item(),
+           "sigma_max": ((s1 - s0).abs() / s0).max().item(),
+           "U": (torch.linalg.matrix_norm(U1 * flip - U0) / torch.linalg.matrix_norm(U0)).item()}
+    if ref.get("V") is not None and got.get("V") is not None:
+        V0, V1 = ref["V"][:, o0], got["V"][:, o1]
+        out["V"] = (torch.linalg.matrix_norm(V1 * flip - V0) / torch.linalg.matrix_norm(V0)).item()
+    return out
+
+
 def cpu_baseline(G_np, p, total_steps, block, target_s):
     """The oracle (same ordering as the GPU path) timed on the first outer steps
     of the same solve; the solve time is extrapolated linearly in steps."""
@@ -282,10 +309,14 @@ def main():
 
     runs = {}
     modes = ["fp64", "mixed"] if args.mode == "both" else [args.mode]
+    results = {}
     for mode in modes:
         ms, infos, R = timed(H, ctx, G, p, params(mode), out, args.steps, args.warmup, check)
         acc = None if args.no_accuracy else accuracy(G, p, R, lam)
         runs[mode] = (ms, infos, acc)
+        if not args.no_accuracy and len(modes) > 1:
+            # the output buffers are shared between the modes
+            results[mode] = {k: (R[k].clone() if R[k] is not None else None) for k in ("sigma", "U", "V")}
     head = "mixed" if "mixed" in runs else modes[0]
     ms, infos, acc = runs[head]
     last = infos[-1]
@@ -321,6 +352,10 @@ def main():
                       "roofline": roofline(m_infos, H.KERNEL_NAMES, peaks, args.workload, variant(mode)),
                       "accuracy": m_acc}
         line["speedup_vs_" + mode] = m_ms / ms
+    if "fp64" in results and "mixed" in results:
+        # the mixed path against the FP64 path on the same input (the FP64
+        # path is held to the oracle at the sizes the oracle runs in seconds)
+        line["mixed_vs_fp64"] = canonical_diff(results["fp64"], results["mixed"], p)
     if args.batched > 0:
         line["batched"] = batched_line(H, W, ctx, args.batched)
     if not args.no_cpu_baseline:

@@ -173,14 +173,17 @@ def workload(name: str):
         return graded(1024, 1e8), 768
     if name == "graded1024_definite":
         return graded(1024, 1e8), 1024
-    if name == "colscaled4096":
-        return colscaled(4096, 4.0), 2048
+    if name.startswith("colscaled") and name[9:].isdigit():
+        n = int(name[9:])
+        return colscaled(n, 4.0), n // 2
     if name.startswith("eigen"):
         # eigen<n>: the paper's test-matrix kind at order n (about equal signs)
         G, p, _ = eigen(int(name[5:]))
         return G, p
-    if name.startswith("graded4096_k"):
+    if name.startswith("graded") and "_k" in name:
+        # graded<n>_k<kappa>[_p<p/n>]
+        n = int(name[6:name.index("_k")])
         kappa = float(name.split("_k")[1].split("_")[0])
         frac = float(name.split("_p")[1]) if "_p" in name else 0.5
-        return graded(4096, kappa), int(round(4096 * frac))
+        return graded(n, kappa), int(round(n * frac))
     raise KeyError(name)

@@ -1,0 +1,51 @@
+"""The block path at n = 8192 (GPU): the largest order of the mixed-precision
+workloads.  No oracle run at this size: the invariants, both precisions, and
+the mixed result against the FP64 one."""
+import numpy as np
+import pytest
+
+from gpu_util import check_invariants_gpu, say
+from paper_1008_1371_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _canon(R, p):
+    import torch
+    s = R["sigma"]
+    idx = torch.arange(s.numel(), device=s.device)
+    o = torch.cat([idx[:p][torch.argsort(-s[:p], stable=True)], idx[p:][torch.argsort(-s[p:], stable=True)]])
+    return s[o], R["U"][:, o], R["V"][:, o]
+
+
+@pytest.mark.timeout(900)
+def test_colscaled8192_both_precisions(hsvd_ctx):
+    """Column-scaled Gaussian n = 8192, p = 4096 (condition ~1e4), mixed and
+    FP64.  Here every block pair's V update runs as one tile of the inner
+    launch (128 block pairs, 128 free CUs)."""
+    import torch
+
+    from paper_1008_1371_amd import hsvd as H
+    G, p = W.workload("colscaled8192")
+    n = G.shape[0]
+    Gt = torch.from_numpy(G).cuda()
+    tol = 1e-15 * n
+    res = {}
+    for prec in (1, 0):
+        R = H.hsvd_solve(hsvd_ctx, Gt, p, H.hsvd_default_params(algo=2, precision=prec), check=False)
+        i = R["info"]
+        say("colscaled8192 precision", prec, "status", R["status"], "sweeps", i["sweeps_fp32"], i["sweeps"],
+            "ms", i["ms_total"])
+        assert R["status"] == 0
+        check_invariants_gpu(Gt, p, R, tol=tol, sweeps=i["sweeps"] + i["sweeps_fp32"])
+        res[prec] = R
+    s1, U1, V1 = _canon(res[1], p)
+    s0, U0, V0 = _canon(res[0], p)
+    es = (torch.linalg.vector_norm(s1 - s0) / torch.linalg.vector_norm(s0)).item()
+    rows = U0.abs().argmax(dim=0)
+    cols = torch.arange(n, device=U0.device)
+    flip = torch.sign(U0[rows, cols]) * torch.sign(U1[rows, cols])
+    eu = (torch.linalg.matrix_norm(U1 * flip - U0) / torch.linalg.matrix_norm(U0)).item()
+    ev = (torch.linalg.matrix_norm(V1 * flip - V0) / torch.linalg.matrix_norm(V0)).item()
+    say("mixed vs fp64: sigma", es, "U", eu, "V", ev)
+    assert es <= 1e-12
