@@ -280,7 +280,10 @@ def main():
     G_np, p = W.workload(args.workload)
     n = G_np.shape[0]
     # the prescribed spectrum of an eigen workload (cached by the generator)
-    lam = W.eigen(n)[2] if args.workload.startswith("eigen") else None
+    lam = None
+    if args.workload.startswith("eigen"):
+        body = args.workload[5:]
+        lam = W.eigen(n, npos=int(body.split("_p")[1]) if "_p" in body else None)[2]
     dev = torch.device("cuda:0")
     G = torch.from_numpy(np.asfortranarray(G_np)).to(dev)
     ctx = H.Context(0)

@@ -470,7 +470,8 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
 
 // Newton-Schulz J-re-orthogonalisation of X (in w.V, FP64, promoted from the
 // FP32 sweeps) followed by G <- G X.  Uses w.T1, w.T2.
-hsvd_status reorthogonalise(hsvd_ctx *ctx, const Workspace &w, int r, int p, int ldg, int &iters, double &resid)
+hsvd_status reorthogonalise(hsvd_ctx *ctx, const Workspace &w, int n, int r, int p, int ldg, int &iters,
+                            double &resid)
 {
     hipStream_t st = ctx->stream;
     if (!ctx->blas) {
@@ -481,8 +482,10 @@ hsvd_status reorthogonalise(hsvd_ctx *ctx, const Workspace &w, int r, int p, int
     iters = 0;
     resid = 1.0;
     double prev = 2.0;
-    // residual at the level of the rounding of the products themselves
-    const double floor_ = 16.0 * r * 0x1p-53;
+    // residual at the level of the rounding of the products themselves: the
+    // n real columns (the bordering columns are exact unit vectors and add
+    // no rounding)
+    const double floor_ = 16.0 * n * 0x1p-53;
     for (int it = 0; it < 6; ++it) {
         HSVD_TRY(launch_rowsign(st, w.V, w.T1, p, ldg, r));  // T1 = J X
         BLAS_TRY(rocblas_dgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, r, r, r, &one, w.V,
@@ -747,7 +750,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
                 // back to FP64: X = J-orthogonalised V32, G1 = G X, V0 = X
                 HSVD_TRY(hipEventRecord(ev[2], st));
                 HSVD_TRY(launch_promote(st, w.V32, w.V, ldg, r));
-                s = reorthogonalise(ctx, w, r, p, ldg, ns_iters, ns_resid);
+                s = reorthogonalise(ctx, w, n, r, p, ldg, ns_iters, ns_resid);
                 if (s != HSVD_OK) return s;
                 HSVD_TRY(hipEventRecord(ev[3], st));
                 HSVD_TRY(hipStreamSynchronize(st));

@@ -177,8 +177,11 @@ def workload(name: str):
         n = int(name[9:])
         return colscaled(n, 4.0), n // 2
     if name.startswith("eigen"):
-        # eigen<n>: the paper's test-matrix kind at order n (about equal signs)
-        G, p, _ = eigen(int(name[5:]))
+        # eigen<n>: the paper's test-matrix kind at order n (about equal
+        # signs); eigen<n>_p<k>: exactly k positive eigenvalues (Table 5.3)
+        body = name[5:]
+        npos = int(body.split("_p")[1]) if "_p" in body else None
+        G, p, _ = eigen(int(body.split("_p")[0]), npos=npos)
         return G, p
     if name.startswith("graded") and "_k" in name:
         # graded<n>_k<kappa>[_p<p/n>]

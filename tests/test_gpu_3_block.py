@@ -51,8 +51,8 @@ def _gate(G, p, res, ref, uv_gate=1e-12):
     pins.check_invariants(G, p, res, tol=ref["tol"])
 
 
-@pytest.mark.parametrize("n,p", [(64, 32), (128, 64), (128, 0), (128, 128), (200, 77),
-                                 (333, 300), (512, 256)])
+@pytest.mark.parametrize("n,p", [(1, 1), (2, 1), (5, 0), (33, 20), (63, 63), (64, 32), (128, 64), (128, 0),
+                                 (128, 128), (200, 77), (333, 300), (512, 256)])
 @pytest.mark.parametrize("ordering", ["modmod", "roundrobin"])
 def test_block_small(hsvd_ctx, n, p, ordering):
     G = W.colscaled(n, 2.0, seed=60 + n)

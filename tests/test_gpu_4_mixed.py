@@ -17,7 +17,7 @@ def _mixed(ctx, G, p, **kw):
     return run_lib(ctx, G, p, precision=1, **kw)
 
 
-@pytest.mark.parametrize("n,p", [(128, 64), (200, 200), (256, 37)])
+@pytest.mark.parametrize("n,p", [(3, 2), (40, 17), (128, 64), (200, 200), (256, 37)])
 def test_mixed_gaussian(hsvd_ctx, n, p):
     G = W.gaussian(n, seed=300 + n)
     spread, ref = ordering_spread(G, p, block=32)
