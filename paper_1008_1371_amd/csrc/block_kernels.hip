@@ -6,14 +6,18 @@
 // each block pair the 2b columns G_P = [G_I G_J] (gathered through rho) are
 // processed in three launches:
 //
-//   block_gram_kernel    A_P = G_P^T G_P on v_mfma_f64_16x16x4f64, split over
-//                        row ranges; partial Grams summed in a fixed order.
-//   block_inner_kernel   one workgroup per pair: A_P and the accumulated
-//                        transformation W in LDS; rotations of the pointwise
+//   block_gram_kernel    A_P = G_P^T G_P on 16x16x4 MFMA, split over row
+//                        ranges; partial Grams summed in a fixed order.
+//   block_inner_*_kernel one workgroup per pair: rotations of the pointwise
 //                        method (eqs. 2.2-2.5, in the short-chain form of
 //                        rotation_params_fast) applied two-sided to A_P and to
-//                        the columns of W, in a parallel inner ordering.
-//   block_update_kernel  [G_P | V_P] <- [G_P | V_P] W on MFMA, row tiles.
+//                        the columns of the accumulated W, in a parallel inner
+//                        ordering (circle kernel: A_P and W in LDS; cross
+//                        kernel: both in registers).  With V carried, extra
+//                        workgroups of the cross kernel apply the previous
+//                        step's W to V.
+//   block_update_kernel  [G_P | V_P] <- [G_P | V_P] W on MFMA, row tiles
+//                        (G alone when V's half runs in the inner launch).
 //
 // Inner ordering: in the first outer step of a sweep every pair of the 2b
 // columns once (circle method over 2b indices, 2b - 1 inner steps); in the
