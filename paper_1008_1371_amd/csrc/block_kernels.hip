@@ -443,9 +443,14 @@ __global__ __launch_bounds__(1024) void block_inner_circle_kernel(BlockArgsT<T> 
 // {L_s2, R_s2(u)}, is held by thread (s1, s2) = (tid / b, tid % b) and shifts
 // along s2 by a lane shuffle.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a)
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void block_inner_cross_kernel(BlockArgsT<T> a)
 {
+    // NT threads; thread tid holds the K blocks (d, s) at positions
+    // tid + NT q, q < K: one slot s = tid % b for all of them, diagonals NT/b
+    // apart, every slot shift inside the thread's half-wave as with K = 1.
+    constexpr int K = (kB * kB) / NT;
+    static_assert(K * NT == kB * kB && NT % 64 == 0, "thread count");
     // A_P staging at the start, the two LR / RL exchange buffers in the loop
     __shared__ double buf[kB2 * kLd];
     // per slot (t, c), c negated for an applied trigonometric rotation (whose
@@ -453,9 +458,11 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
     // bulk of an inner step
     __shared__ double2 prm[2][kB];
     __shared__ int rotf[2][kB];  // slot rotated (read by the diagonal blocks)
-    if ((int)blockIdx.x >= a.nb / 2) {
-        v_update_role(a, (int)blockIdx.x - a.nb / 2);
-        return;
+    if constexpr (NT == kB * kB) {
+        if ((int)blockIdx.x >= a.nb / 2) {
+            v_update_role(a, (int)blockIdx.x - a.nb / 2);
+            return;
+        }
     }
     if (!bind_problem(a)) return;
     const int k = blockIdx.x;
@@ -463,31 +470,33 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
     const int lane = tid & 63;
     const int2 IJ = outer_pair(a, k);
 
-    // A_P = sum of the partial Grams in split order.  Thread tid sums entries
-    // (x, y0 .. y0 + 3), x = tid / 16, y0 = 4 (tid % 16), of every split with
+    // A_P = sum of the partial Grams in split order.  Work item i sums entries
+    // (x, y0 .. y0 + 3), x = i / 16, y0 = 4 (i % 16), of every split with
     // vector loads; only the upper-triangular 16 x 16 tiles hold data.
-    {
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
         typedef T v4 __attribute__((ext_vector_type(4)));
         constexpr int kChunk = sizeof(T) == 4 ? 16 : 8;
-        const int x = tid >> 4, y0 = (tid & 15) * 4;
+        const int item = tid + NT * q;
+        const int x = item >> 4, y0 = (item & 15) * 4;
         if ((y0 >> 4) >= (x >> 4)) {
             const T *P = a.partial + (size_t)k * a.splits * (kB2 * kB2) + x * kB2 + y0;
             double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
             for (int base = 0; base < a.splits; base += kChunk) {
                 v4 v[kChunk];
 #pragma unroll
-                for (int q = 0; q < kChunk; ++q)
-                    v[q] = base + q < a.splits
-                               ? *reinterpret_cast<const v4 *>(P + (size_t)(base + q) * (kB2 * kB2))
+                for (int c = 0; c < kChunk; ++c)
+                    v[c] = base + c < a.splits
+                               ? *reinterpret_cast<const v4 *>(P + (size_t)(base + c) * (kB2 * kB2))
                                : v4{0, 0, 0, 0};
 #pragma unroll
-                for (int q = 0; q < kChunk; ++q)
-                    if (base + q < a.splits) {
-                        const bool first = base + q == 0;
-                        g0 = first ? (double)v[q][0] : g0 + (double)v[q][0];
-                        g1 = first ? (double)v[q][1] : g1 + (double)v[q][1];
-                        g2 = first ? (double)v[q][2] : g2 + (double)v[q][2];
-                        g3 = first ? (double)v[q][3] : g3 + (double)v[q][3];
+                for (int c = 0; c < kChunk; ++c)
+                    if (base + c < a.splits) {
+                        const bool first = base + c == 0;
+                        g0 = first ? (double)v[c][0] : g0 + (double)v[c][0];
+                        g1 = first ? (double)v[c][1] : g1 + (double)v[c][1];
+                        g2 = first ? (double)v[c][2] : g2 + (double)v[c][2];
+                        g3 = first ? (double)v[c][3] : g3 + (double)v[c][3];
                     }
             }
             double *row = buf + x * kLd + y0;
@@ -498,23 +507,37 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
         }
     }
     __syncthreads();
-    const int d = tid >> 5, s = tid & 31;
-    const int s1 = s, s2 = (s + d) & 31;
-    // entry (x, y) is read at (min, max) for both mirror positions
-    double LL = buf[min(s1, s2) * kLd + max(s1, s2)];
-    double LR = buf[s1 * kLd + kB + s2];
-    double RL = buf[s2 * kLd + kB + s1];
-    double RR = buf[(kB + min(s1, s2)) * kLd + kB + max(s1, s2)];
-    const bool diag = d == 0;
-    const bool cf = s1 <= s2;
-    const int w1 = tid >> 5, w2 = tid & 31;  // W block of this thread
-    double W0L = w1 == w2 ? 1.0 : 0.0, W0R = 0.0, W1L = 0.0, W1R = w1 == w2 ? 1.0 : 0.0;
-    const int nxt = (lane & 32) | ((lane + 1) & 31);           // lane of (d, s + 1), resp. W column s2 + 1
-    const int lr_cell = (((d + 1) & 31) << 5) | s;             // thread (d + 1, s)
-    const int rl_cell = (((d + 31) & 31) << 5) | ((s + 1) & 31);  // thread (d - 1, s + 1)
-    double *const xlr = buf, *const xrl = buf + 2 * kB * kB;    // [2][b * b] each
-    // pivots of slot s (lanes 0 .. b-1 of the first wave)
-    double pll = LL, plr = LR, prr = RR;
+    const int s = tid & 31;
+    const int s1 = s;
+    double LL[K], LR[K], RL[K], RR[K];
+    double W0L[K], W0R[K], W1L[K], W1R[K];
+    int s2[K], lr_cell[K], rl_cell[K];
+    bool cf[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const int pos = tid + NT * q;
+        const int d = pos >> 5;
+        s2[q] = (s + d) & 31;
+        cf[q] = s1 <= s2[q];
+        // entry (x, y) is read at (min, max) for both mirror positions
+        LL[q] = buf[min(s1, s2[q]) * kLd + max(s1, s2[q])];
+        LR[q] = buf[s1 * kLd + kB + s2[q]];
+        RL[q] = buf[s2[q] * kLd + kB + s1];
+        RR[q] = buf[(kB + min(s1, s2[q])) * kLd + kB + max(s1, s2[q])];
+        // W block of this position: rows {w1, b + w1} (w1 = d) by columns
+        // {L_w2, R_w2} (w2 = s)
+        W0L[q] = d == s ? 1.0 : 0.0;
+        W0R[q] = 0.0;
+        W1L[q] = 0.0;
+        W1R[q] = d == s ? 1.0 : 0.0;
+        lr_cell[q] = (((d + 1) & 31) << 5) | s;             // position (d + 1, s)
+        rl_cell[q] = (((d + 31) & 31) << 5) | ((s + 1) & 31);  // position (d - 1, s + 1)
+    }
+    const bool diag = tid < kB;  // position (0, s), q = 0
+    const int nxt = (lane & 32) | ((lane + 1) & 31);  // lane of (d, s + 1), resp. W column s2 + 1
+    double *const xlr = buf, *const xrl = buf + 2 * kB * kB;  // [2][b * b] each
+    // pivots of slot s (lanes 0 .. b-1 of the first wave, q = 0)
+    double pll = LL[0], plr = LR[0], prr = RR[0];
     int code = 0, nrot = 0, nskip = 0, rank = 0;
     double maxt = 0.0;
     unsigned long long tmask = 0ull;  // local columns touched by a rotation (first wave)
@@ -552,65 +575,75 @@ __global__ __launch_bounds__(1024) void block_inner_cross_kernel(BlockArgsT<T> a
             rotf[pb][s] = rot;
         }
         __syncthreads();
-        if (u > 0) {
-            // LR and RL of the shift to this step
-            LR = xlr[(pb ^ 1) * (kB * kB) + lr_cell];
-            RL = xrl[(pb ^ 1) * (kB * kB) + rl_cell];
-        }
-        // slots s1 and s2; W's column slot w2 is s1.  (t, c, h) with h = -t
-        // for a trigonometric rotation
-        const double2 r1 = prm[pb][s1], r2 = prm[pb][s2];
+        // slot s1 = s is common to the thread's positions; W's column slot
+        // w2 is s1.  (t, c, h) with h = -t for a trigonometric rotation
+        const double2 r1 = prm[pb][s1];
         const double3 p1 = make_double3(r1.x, fabs(r1.y), r1.y < 0.0 ? -r1.x : r1.x);
-        const double3 p2 = make_double3(r2.x, fabs(r2.y), r2.y < 0.0 ? -r2.x : r2.x);
-        // A block, rows by slot s1, columns by slot s2.  Columns first iff
-        // s1 <= s2; otherwise the same column-then-row sequence runs on the
-        // transposed block with the slots exchanged, which is the
-        // row-then-column order on the block itself.
-        const double3 pa = cf ? p2 : p1, pq = cf ? p1 : p2;
-        {
-            const double x01 = cf ? LR : RL, x10 = cf ? RL : LR;
-            const double f00 = fma(pa.z, x01, LL) * pa.y, f01 = fma(pa.x, LL, x01) * pa.y;
-            const double f10 = fma(pa.z, RR, x10) * pa.y, f11 = fma(pa.x, x10, RR) * pa.y;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            if (u > 0) {
+                // LR and RL of the shift to this step
+                LR[q] = xlr[(pb ^ 1) * (kB * kB) + lr_cell[q]];
+                RL[q] = xrl[(pb ^ 1) * (kB * kB) + rl_cell[q]];
+            }
+            const double2 r2 = prm[pb][s2[q]];
+            const double3 p2 = make_double3(r2.x, fabs(r2.y), r2.y < 0.0 ? -r2.x : r2.x);
+            // A block, rows by slot s1, columns by slot s2.  Columns first iff
+            // s1 <= s2; otherwise the same column-then-row sequence runs on
+            // the transposed block with the slots exchanged, which is the
+            // row-then-column order on the block itself.
+            const double3 pa = cf[q] ? p2 : p1, pq = cf[q] ? p1 : p2;
+            const double x01 = cf[q] ? LR[q] : RL[q], x10 = cf[q] ? RL[q] : LR[q];
+            const double f00 = fma(pa.z, x01, LL[q]) * pa.y, f01 = fma(pa.x, LL[q], x01) * pa.y;
+            const double f10 = fma(pa.z, RR[q], x10) * pa.y, f11 = fma(pa.x, x10, RR[q]) * pa.y;
             const double y00 = fma(pq.z, f10, f00) * pq.y, y10 = fma(pq.x, f00, f10) * pq.y;
             const double y01 = fma(pq.z, f11, f01) * pq.y, y11 = fma(pq.x, f01, f11) * pq.y;
-            LL = y00;
-            RR = y11;
-            LR = cf ? y01 : y10;
-            RL = cf ? y10 : y01;
+            LL[q] = y00;
+            RR[q] = y11;
+            LR[q] = cf[q] ? y01 : y10;
+            RL[q] = cf[q] ? y10 : y01;
         }
         if (diag && rotf[pb][s1]) {
-            LR = 0.0;
-            RL = 0.0;
+            LR[0] = 0.0;
+            RL[0] = 0.0;
         }
         if (u + 1 < kB) {
-            xlr[pb * (kB * kB) + tid] = LR;
-            xrl[pb * (kB * kB) + tid] = RL;
-            RR = __shfl(RR, nxt, 64);
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                xlr[pb * (kB * kB) + tid + NT * q] = LR[q];
+                xrl[pb * (kB * kB) + tid + NT * q] = RL[q];
+                RR[q] = __shfl(RR[q], nxt, 64);
+            }
             if (tid < 64) {
                 // next pivots: a_LL of (s, s), a_LR of (s, s + 1) (lane b + s),
                 // a_RR of (s + 1, s + 1) (just shifted in)
-                plr = __shfl(LR, kB + (lane & 31), 64);
-                pll = LL;
-                prr = RR;
+                plr = __shfl(LR[0], kB + (lane & 31), 64);
+                pll = LL[0];
+                prr = RR[0];
             }
         }
         // W <- W R on columns (L_w2, R_w2), then the shift of its R half
-        {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
             const double3 pw = p1;
-            const double a0 = fma(pw.z, W0R, W0L) * pw.y, b0 = fma(pw.x, W0L, W0R) * pw.y;
-            const double a1 = fma(pw.z, W1R, W1L) * pw.y, b1 = fma(pw.x, W1L, W1R) * pw.y;
-            W0L = a0;
-            W1L = a1;
-            W0R = __shfl(b0, nxt, 64);
-            W1R = __shfl(b1, nxt, 64);
+            const double a0 = fma(pw.z, W0R[q], W0L[q]) * pw.y, b0 = fma(pw.x, W0L[q], W0R[q]) * pw.y;
+            const double a1 = fma(pw.z, W1R[q], W1L[q]) * pw.y, b1 = fma(pw.x, W1L[q], W1R[q]) * pw.y;
+            W0L[q] = a0;
+            W1L[q] = a1;
+            W0R[q] = __shfl(b0, nxt, 64);
+            W1R[q] = __shfl(b1, nxt, 64);
         }
     }
     // after b shifts the slots are back in natural order: R_s = b + s
     T *Wg = a.W + (size_t)k * (kB2 * kB2);
-    Wg[w1 * kB2 + w2] = (T)W0L;
-    Wg[w1 * kB2 + kB + w2] = (T)W0R;
-    Wg[(kB + w1) * kB2 + w2] = (T)W1L;
-    Wg[(kB + w1) * kB2 + kB + w2] = (T)W1R;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const int w1 = (tid + NT * q) >> 5, w2 = s;
+        Wg[w1 * kB2 + w2] = (T)W0L[q];
+        Wg[w1 * kB2 + kB + w2] = (T)W0R[q];
+        Wg[(kB + w1) * kB2 + w2] = (T)W1L[q];
+        Wg[(kB + w1) * kB2 + kB + w2] = (T)W1R[q];
+    }
     if (tid < 64) {
         // counters of the b slots, reduced within the first wave
         unsigned rot_sum = (unsigned)nrot, skip_sum = (unsigned)nskip;
@@ -967,7 +1000,13 @@ hipError_t launch_block_inner(hipStream_t st, const BlockArgsT<T> &a)
         return hipGetLastError();
     }
     if (a.vprev_wgs > 0 && a.nprob > 1) return hipErrorInvalidValue;
-    block_inner_cross_kernel<T><<<dim3(a.nb / 2 + a.vprev_wgs, 1, a.nprob), 1024, 0, st>>>(a);
+    if (a.nprob > 1) {
+        // batched: throughput over latency -- 256 threads per block pair, four
+        // pairs per CU, each thread four blocks of A_P
+        block_inner_cross_kernel<T, 256><<<dim3(a.nb / 2, 1, a.nprob), 256, 0, st>>>(a);
+    } else {
+        block_inner_cross_kernel<T, kB * kB><<<dim3(a.nb / 2 + a.vprev_wgs, 1, a.nprob), kB * kB, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 
