@@ -236,22 +236,26 @@ def timed(H, ctx, G, p, prm, out, steps, warmup, check):
 
 
 def batched_line(H, W, ctx, count):
+    """The batched solver on `count` Gaussian problems, n ~ U{8..256}, FP64 and
+    mixed precision."""
     import numpy as np
     import torch
     ns, ps, Gs = W.batch(count)
     flat, offs = W.pack_batch(Gs)
     voffs = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
     Gd = torch.from_numpy(flat).cuda()
-    prm = H.hsvd_default_params()
-    H.hsvd_solve_batched(ctx, ns, ps, Gd, offs, voffs, prm)  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    R = H.hsvd_solve_batched(ctx, ns, ps, Gd, offs, voffs, prm)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return {"problems": count, "n_range": [int(ns.min()), int(ns.max())], "seconds": dt,
-            "solves_per_s": count / dt, "max_sweeps": R["info"]["sweeps"],
-            "all_converged": bool((R["statuses"] == 0).all())}
+    out = {"problems": count, "n_range": [int(ns.min()), int(ns.max())]}
+    for name, prec in (("fp64", H.FP64), ("mixed", H.MIXED)):
+        prm = H.hsvd_default_params(precision=prec)
+        H.hsvd_solve_batched(ctx, ns, ps, Gd, offs, voffs, prm)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R = H.hsvd_solve_batched(ctx, ns, ps, Gd, offs, voffs, prm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"seconds": dt, "solves_per_s": count / dt, "max_sweeps_fp32": R["info"]["sweeps_fp32"],
+                     "max_sweeps": R["info"]["sweeps"], "all_converged": bool((R["statuses"] == 0).all())}
+    return out
 
 
 def main():

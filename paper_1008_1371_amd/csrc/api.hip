@@ -1003,6 +1003,101 @@ extern "C" hsvd_status hsvd_autotune(hsvd_ctx *ctx, int n, int *best_algo, int *
     return HSVD_OK;
 }
 
+// FP32 phase of a batched mixed solve for one group, then the
+// J-re-orthogonalisation of each problem's V and G1 = G X -- the steps of a
+// single mixed solve, per problem.  FP32 block sweeps run until every problem
+// has left FP32 by its own switch rule (a problem out of FP32 is skipped by
+// the later FP32 launches); the Newton-Schulz iteration runs on the whole
+// group with strided batched GEMMs, each problem applying its corrections
+// until its own residual stops falling quadratically.  The FP64 sweeps then
+// start from (G1, V0 = X).
+static hsvd_status batch_mixed_phase(hsvd_ctx *ctx, hipStream_t st, const BatchGroup &g, const BatchMixed &m,
+                                     const BlockArgsT<double> &ba, int4 *S2, int pairs, int steps_per_sweep,
+                                     int max_sweeps, bool sort, long long &gstep, int *host_active, int &sweeps32)
+{
+    HSVD_TRY(launch_batch_mixed_init(st, g, m));
+    BlockArgsT<float> fa;
+    fa.G = m.G32;
+    fa.V = m.V32;
+    fa.ldg = ba.ldg;
+    fa.r = ba.r;
+    fa.p = 0;
+    fa.nb = ba.nb;
+    fa.rho = ba.rho;
+    fa.ordering = ba.ordering;
+    // the FP32 partial Grams and W in the space of the FP64 ones
+    fa.partial = reinterpret_cast<float *>(ba.partial);
+    fa.splits = ba.splits;
+    fa.rows_per_split = ba.rows_per_split;
+    fa.W = reinterpret_cast<float *>(ba.W);
+    fa.active = ba.active;
+    fa.C = ba.C;
+    fa.nrot = ba.nrot;
+    fa.nskip = ba.nskip;
+    fa.nact = ba.nact;
+    fa.ntc = ba.ntc;
+    fa.maxt = ba.maxt;
+    fa.ctl = ba.ctl;
+    fa.tol = 0.0;
+    fa.tthresh = 0.0;
+    fa.inner_sweeps = ba.inner_sweeps;
+    fa.nprob = ba.nprob;
+    fa.done = m.done32;
+    fa.pvec = ba.pvec;
+    fa.tolvec = m.tol32;
+    fa.tthvec = m.tth32;
+    BatchGroup g32 = g;
+    g32.done = m.done32;  // the sort of the FP32 phase skips problems out of it
+    sweeps32 = 0;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+        for (int k = 0; k < steps_per_sweep; ++k, ++gstep) {
+            fa.step = k;
+            fa.S_in = S2 + (gstep & 1) * pairs;
+            fa.S_out = S2 + ((gstep + 1) & 1) * pairs;
+            HSVD_TRY(launch_block_gram<float>(st, fa));
+            HSVD_TRY(launch_block_inner<float>(st, fa));
+            HSVD_TRY(launch_block_update<float>(st, fa));
+        }
+        HSVD_TRY(launch_batch_colnorm32(st, g, m));
+        if (sort) HSVD_TRY(launch_batch_sort(st, g32));
+        HSVD_TRY(launch_batch_decide32(st, g, m));
+        HSVD_TRY(hipMemcpyAsync(host_active, g.active_count, sizeof(int), hipMemcpyDeviceToHost, st));
+        HSVD_TRY(hipStreamSynchronize(st));
+        ++sweeps32;
+        if (*host_active == 0) break;
+    }
+    // V = V32 promoted; Newton-Schulz X <- X (3I - J X^T J X) / 2 per problem
+    HSVD_TRY(launch_batch_promote(st, g, m));
+    if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success) return HSVD_E_DEVICE;
+    BLAS_TRY(rocblas_set_stream(ctx->blas, st));
+    const double one = 1.0, zero = 0.0;
+    const int r = g.r, ld = g.ldg;
+    const rocblas_stride mat = (rocblas_stride)g.ldg * g.r;
+    for (int it = 0; it < 6; ++it) {
+        HSVD_TRY(launch_batch_rowsign(st, g, m));  // T1 = J X
+        BLAS_TRY(rocblas_dgemm_strided_batched(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, r, r,
+                                               r, &one, g.V, ld, mat, m.T1, ld, mat, &zero, m.T2, ld, mat,
+                                               g.nprob));  // T2 = X^T J X
+        HSVD_TRY(launch_batch_ns_form(st, g, m));           // T2 = (3I - J X^T J X) / 2, residuals
+        HSVD_TRY(launch_batch_ns_decide(st, g, m, it));
+        HSVD_TRY(hipMemcpyAsync(host_active, g.active_count, sizeof(int), hipMemcpyDeviceToHost, st));
+        HSVD_TRY(hipStreamSynchronize(st));
+        if (*host_active == 0) break;
+        BLAS_TRY(rocblas_dgemm_strided_batched(ctx->blas, rocblas_operation_none, rocblas_operation_none, r, r, r,
+                                               &one, g.V, ld, mat, m.T2, ld, mat, &zero, m.T1, ld, mat,
+                                               g.nprob));  // T1 = X T2
+        HSVD_TRY(launch_batch_copy_if(st, g, m.T1, g.V, m.apply, false));
+    }
+    // G1 = G X for every running problem
+    BLAS_TRY(rocblas_dgemm_strided_batched(ctx->blas, rocblas_operation_none, rocblas_operation_none, r, r, r, &one,
+                                           g.G, ld, mat, g.V, ld, mat, &zero, m.T1, ld, mat, g.nprob));
+    HSVD_TRY(launch_batch_copy_if(st, g, m.T1, g.G, g.done, true));
+    // the kept diagonal of G1 and the sort, as after a sweep
+    HSVD_TRY(launch_batch_colnorm(st, g, false));
+    if (sort) HSVD_TRY(launch_batch_sort(st, g));
+    return HSVD_OK;
+}
+
 extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n, const int *p,
                                           const long long *off, const long long *voff, const double *G,
                                           const hsvd_params *prm_in, double *sigma, double *U, double *V,
@@ -1015,12 +1110,15 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
     hsvd_params prm;
     if (prm_in) prm = *prm_in;
     else hsvd_default_params(&prm);
-    if (prm.precision != HSVD_FP64) return HSVD_E_INVAL;
+    if (prm.precision != HSVD_FP64 && prm.precision != HSVD_MIXED) return HSVD_E_INVAL;
+    const bool mixed = prm.precision == HSVD_MIXED;
     if (prm.ordering != HSVD_ORD_MODMOD && prm.ordering != HSVD_ORD_ROUNDROBIN) return HSVD_E_INVAL;
     if (prm.block != 0 && prm.block != block_width()) return HSVD_E_INVAL;
     if (prm.inner_sweeps < 0 || prm.inner_sweeps > 100) return HSVD_E_INVAL;
     const bool want_v = prm.want_v != 0;
     if (V && !want_v) return HSVD_E_INVAL;
+    // the mixed path carries V through its FP32 phase even when it is not returned
+    const bool acc_v = want_v || mixed;
     for (int k = 0; k < batch; ++k)
         if (n[k] < 1 || n[k] > 1024 || p[k] < 0 || p[k] > n[k] || off[k] < 0 || voff[k] < 0) return HSVD_E_INVAL;
     const int max_sweeps = prm.max_sweeps > 0 ? prm.max_sweeps : 100;
@@ -1040,7 +1138,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
     long long ktimed[HSVD_NKERNELS] = {0};
     double kbytes[HSVD_NKERNELS] = {0}, kflops[HSVD_NKERNELS] = {0};
     long long tot_rot = 0, tot_skip = 0, tot_act = 0, tot_steps = 0;
-    int max_sw = 0;
+    int max_sw = 0, max_sw32 = 0;
     std::vector<int> all_status(batch, HSVD_OK), all_sweeps(batch, 0);
     HSVD_TRY(hipEventRecord(ev[0], st));
     for (size_t gi = 1; gi < groups.size(); ++gi) {
@@ -1059,7 +1157,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         const size_t o_tol = take_bytes(o, sizeof(double) * K), o_tth = take_bytes(o, sizeof(double) * K);
         const size_t o_cnt = take_bytes(o, sizeof(int));
         const size_t o_G = take_bytes(o, sizeof(double) * mat * K);
-        const size_t o_V = take_bytes(o, want_v ? sizeof(double) * mat * K : 0);
+        const size_t o_V = take_bytes(o, acc_v ? sizeof(double) * mat * K : 0);
         const size_t o_d = take_bytes(o, sizeof(double) * r * K), o_dt = take_bytes(o, sizeof(double) * r * K);
         const size_t o_rho = take_bytes(o, sizeof(int) * r * K), o_rt = take_bytes(o, sizeof(int) * r * K);
         const size_t o_C = take_bytes(o, sizeof(int) * pairs * K);
@@ -1073,6 +1171,16 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         const size_t o_P = take_bytes(o, sizeof(double) * pairs * bb * K);
         const size_t o_W = take_bytes(o, sizeof(double) * pairs * bb * K);
         const size_t o_act = take_bytes(o, sizeof(unsigned long long) * pairs * K);
+        // mixed: FP32 copies, the Newton-Schulz products and the per-problem
+        // state (the FP32 partial Grams and W live in the FP64 ones' space)
+        const size_t mx_mat = mixed ? mat * K : 0, mx_k = mixed ? (size_t)K : 0;
+        const size_t o_G32 = take_bytes(o, sizeof(float) * mx_mat), o_V32 = take_bytes(o, sizeof(float) * mx_mat);
+        const size_t o_T1 = take_bytes(o, sizeof(double) * mx_mat), o_T2 = take_bytes(o, sizeof(double) * mx_mat);
+        const size_t o_d32 = take_bytes(o, sizeof(int) * mx_k), o_s32 = take_bytes(o, sizeof(int) * mx_k);
+        const size_t o_pm = take_bytes(o, sizeof(double) * mx_k), o_pf = take_bytes(o, sizeof(double) * mx_k);
+        const size_t o_t32 = take_bytes(o, sizeof(double) * mx_k), o_h32 = take_bytes(o, sizeof(double) * mx_k);
+        const size_t o_ap = take_bytes(o, sizeof(int) * mx_k), o_nd = take_bytes(o, sizeof(int) * mx_k);
+        const size_t o_np = take_bytes(o, sizeof(double) * mx_k);
         s = ensure_ws(ctx, o);
         if (s != HSVD_OK) return s;
         char *base = static_cast<char *>(ctx->ws);
@@ -1116,7 +1224,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         g.sweeps = reinterpret_cast<int *>(base + o_sw);
         g.active_count = reinterpret_cast<int *>(base + o_cnt);
         g.G = reinterpret_cast<double *>(base + o_G);
-        g.V = want_v ? reinterpret_cast<double *>(base + o_V) : nullptr;
+        g.V = acc_v ? reinterpret_cast<double *>(base + o_V) : nullptr;
         g.d = reinterpret_cast<double *>(base + o_d);
         g.dtmp = reinterpret_cast<double *>(base + o_dt);
         g.rho = reinterpret_cast<int *>(base + o_rho);
@@ -1130,7 +1238,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         g.ctl = reinterpret_cast<Ctl *>(base + o_ctl);
         int4 *S2 = reinterpret_cast<int4 *>(base + o_S2);
 
-        HSVD_TRY(launch_batch_setup(st, g, G, want_v));
+        HSVD_TRY(launch_batch_setup(st, g, G, acc_v));
         HSVD_TRY(launch_block_stepper_init(st, S2, nb));
         if (prm.sort) HSVD_TRY(launch_batch_sort(st, g));
 
@@ -1166,6 +1274,27 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         long long gstep = 0;
         int gsweeps = 0;
         int *host_active = &ctx->host_ctl->code;  // pinned scratch for the count of running problems
+        if (mixed) {
+            BatchMixed m;
+            m.G32 = reinterpret_cast<float *>(base + o_G32);
+            m.V32 = reinterpret_cast<float *>(base + o_V32);
+            m.T1 = reinterpret_cast<double *>(base + o_T1);
+            m.T2 = reinterpret_cast<double *>(base + o_T2);
+            m.done32 = reinterpret_cast<int *>(base + o_d32);
+            m.sweeps32 = reinterpret_cast<int *>(base + o_s32);
+            m.prev_maxt = reinterpret_cast<double *>(base + o_pm);
+            m.prev_frac = reinterpret_cast<double *>(base + o_pf);
+            m.tol32 = reinterpret_cast<double *>(base + o_t32);
+            m.tth32 = reinterpret_cast<double *>(base + o_h32);
+            m.apply = reinterpret_cast<int *>(base + o_ap);
+            m.nsdone = reinterpret_cast<int *>(base + o_nd);
+            m.nsprev = reinterpret_cast<double *>(base + o_np);
+            int sw32 = 0;
+            s = batch_mixed_phase(ctx, st, g, m, ba, S2, pairs, steps_per_sweep, max_sweeps, prm.sort != 0, gstep,
+                                  host_active, sw32);
+            if (s != HSVD_OK) return s;
+            max_sw32 = max_sw32 > sw32 ? max_sw32 : sw32;
+        }
         // one sweep: the outer steps, the kept diagonal, the sort, the stop rule
         auto enqueue_sweep = [&](hipStream_t q, bool timed) -> hipError_t {
             for (int k = 0; k < steps_per_sweep; ++k, ++gstep) {
@@ -1288,6 +1417,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         hipEventElapsedTime(&ms, ev[0], ev[1]);
         info->status = result;
         info->sweeps = max_sw;
+        info->sweeps_fp32 = max_sw32;
         info->block = b;
         info->rotations = tot_rot;
         info->skips = tot_skip;

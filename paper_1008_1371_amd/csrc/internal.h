@@ -418,6 +418,31 @@ hipError_t launch_batch_reduce_decide(hipStream_t st, const BatchGroup &g);
 hipError_t launch_batch_finalize(hipStream_t st, const BatchGroup &g, double *sigma, double *U, double *V,
                                  double *lambda);
 
+// Mixed precision over a group of a batched solve: FP32 sweeps on FP32 copies
+// of G and V, each problem leaving them by the switch rule of a single mixed
+// solve, then its V J-re-orthogonalised in FP64 and G1 = G X.
+struct BatchMixed {
+    float *G32, *V32;      // per problem ldg * r
+    int *done32;           // FP32 phase over for the problem
+    int *sweeps32;
+    double *prev_maxt, *prev_frac;
+    double *tol32, *tth32;
+    double *T1, *T2;       // per problem ldg * r (FP64)
+    int *apply;            // the Newton-Schulz correction of this iteration applies
+    int *nsdone;
+    double *nsprev;
+};
+hipError_t launch_batch_mixed_init(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
+hipError_t launch_batch_colnorm32(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
+hipError_t launch_batch_decide32(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
+hipError_t launch_batch_promote(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
+hipError_t launch_batch_rowsign(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
+hipError_t launch_batch_ns_form(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
+hipError_t launch_batch_ns_decide(hipStream_t st, const BatchGroup &g, const BatchMixed &m, int iter);
+// dst_z <- src_z (ldg x r) for the problems with flag[z] != 0 (invert: == 0)
+hipError_t launch_batch_copy_if(hipStream_t st, const BatchGroup &g, const double *src, double *dst,
+                                const int *flag, bool invert);
+
 // mixed path helpers
 hipError_t launch_to_fp32(hipStream_t st, const double *G, float *G32, float *V32, int ldg, int r);
 hipError_t launch_promote(hipStream_t st, const float *X32, double *X, int ldg, int r);

@@ -104,3 +104,46 @@ def test_batched_graph_replay_matches_eager(hsvd_ctx):
             assert np.array_equal(a[k][key], b[k][key]), (k, key)
             assert np.array_equal(a[k][key], c[k][key]), (k, key)
         assert a[k]["sweeps"] == b[k]["sweeps"] == c[k]["sweeps"]
+
+
+def test_batched_mixed_vs_oracle(hsvd_ctx):
+    """Mixed precision over a batch: FP32 block sweeps (each problem leaving
+    them by its own switch rule), the batched J-re-orthogonalisation, FP64
+    refinement.  Each problem against the FP64 oracle: sigma to 1e-12, U and V
+    to 10x the ordering spread (the mixed trajectory is its own)."""
+    from parity import ordering_spread
+    ns, ps, Gs = W.batch(30, lo=8, hi=200, seed_sizes=78, seed_g=9100)
+    say("batched mixed", list(ns))
+    R, res = _run(hsvd_ctx, ns, ps, Gs, precision=1)
+    assert R["status"] == 0, R["statuses"]
+    assert R["info"]["sweeps_fp32"] >= 1
+    for k, (n, p, G) in enumerate(zip(ns, ps, Gs)):
+        spread, ref = ordering_spread(G, int(p), block=32)
+        e = compare(res[k], ref, int(p))
+        gate = max(1e-12, 10 * max(spread["U"], spread["V"]))
+        assert e["sigma_norm"] <= 1e-12 and e["U"] <= gate and e["V"] <= gate, (k, n, p, e, spread)
+        r = dict(res[k])
+        r["sweeps"] = res[k]["sweeps"] + R["info"]["sweeps_fp32"]
+        pins.check_invariants(G, int(p), r, tol=1e-15 * n)
+
+
+def test_batched_mixed_edge_and_no_v(hsvd_ctx):
+    """Mixed batch with n = 1, definite signatures and a rank-deficient
+    problem (failure local to it), and without V: sigma equal to the run with
+    V."""
+    g = np.random.Generator(np.random.PCG64(5))
+    Gs = [g.standard_normal((n, n)) for n in (1, 7, 64, 65, 130)]
+    Gs[3][:, 5] = Gs[3][:, 9]  # duplicate columns: numerically rank deficient
+    ns = np.array([1, 7, 64, 65, 130], np.int32)
+    ps = np.array([1, 0, 64, 30, 65], np.int32)
+    R, res = _run(hsvd_ctx, ns, ps, Gs, precision=1)
+    say("mixed edge statuses", R["statuses"], "sweeps", R["sweeps"], R["info"]["sweeps_fp32"])
+    from paper_1008_1371_amd import hsvd as H
+    assert [int(x) for x in R["statuses"]][:3] == [0, 0, 0] and int(R["statuses"][4]) == 0
+    assert int(R["statuses"][3]) in (0, H.E_RANK)
+    for k in (0, 1, 2, 4):
+        ref = oracle.hsvd(Gs[k], int(ps[k]))
+        assert np.allclose(np.sort(res[k]["sigma"]), np.sort(ref["sigma"]), rtol=1e-12, atol=0)
+    R2, res2 = _run(hsvd_ctx, ns, ps, Gs, precision=1, want_v=0)
+    for k in (0, 1, 2, 4):
+        assert np.allclose(np.sort(res2[k]["sigma"]), np.sort(res[k]["sigma"]), rtol=1e-12, atol=0)
