@@ -152,7 +152,10 @@ hsvd_status hsvd_solve_j(hsvd_ctx *ctx, const double *G, int lda, int n, const s
 
 /* Batched solves: `batch` independent problems G_k (n[k] x n[k], 1 <= n[k] <= 1024,
  * J_k = diag(I_p[k], -I_{n[k]-p[k]})), each solved as by hsvd_solve with the block
- * path (FP64) and its own tolerance (prm->tol <= 0: 1e-15 n[k]) and stop rule.
+ * path and its own tolerance (prm->tol <= 0: 1e-15 n[k]) and stop rule, in FP64
+ * or (prm->precision = HSVD_MIXED) with FP32 sweeps first, each problem leaving
+ * them by its own switch rule, then the J-re-orthogonalisation of its V and
+ * FP64 refinement sweeps.
  *   n, p, off, voff  host arrays of `batch` entries: order, number of +1 signs,
  *                    element offset of G_k / U_k / V_k in the packed matrices
  *                    (column-major, leading dimension n[k]), element offset of
@@ -162,7 +165,8 @@ hsvd_status hsvd_solve_j(hsvd_ctx *ctx, const double *G, int lda, int n, const s
  *                    V requires prm->want_v).
  *   status, sweeps   host arrays of `batch` ints (may be NULL): each problem's
  *                    hsvd_status and sweep count.
- *   info             host, may be NULL: totals over the batch (sweeps = largest).
+ *   info             host, may be NULL: totals over the batch (sweeps and
+ *                    sweeps_fp32 = largest; per-problem sweeps are FP64 sweeps).
  * Problems are grouped by their bordered order (a multiple of 2b); each group
  * runs as one sequence of launches that covers all of its problems.  Returns
  * HSVD_OK when every problem converged, else the status of the first problem
