@@ -458,6 +458,7 @@ __global__ __launch_bounds__(NT) void block_inner_cross_kernel(BlockArgsT<T> a)
     // bulk of an inner step
     __shared__ double2 prm[2][kB];
     __shared__ int rotf[2][kB];  // slot rotated (read by the diagonal blocks)
+    __shared__ int live;         // some cross pair fails the skip test
     if constexpr (NT == kB * kB) {
         if ((int)blockIdx.x >= a.nb / 2) {
             v_update_role(a, (int)blockIdx.x - a.nb / 2);
@@ -506,6 +507,7 @@ __global__ __launch_bounds__(NT) void block_inner_cross_kernel(BlockArgsT<T> a)
             row[3] = g3;
         }
     }
+    if (tid == 0) live = 0;
     __syncthreads();
     const int s = tid & 31;
     const int s1 = s;
@@ -534,6 +536,20 @@ __global__ __launch_bounds__(NT) void block_inner_cross_kernel(BlockArgsT<T> a)
         rl_cell[q] = (((d + 31) & 31) << 5) | ((s + 1) & 31);  // position (d - 1, s + 1)
     }
     const bool diag = tid < kB;  // position (0, s), q = 0
+    const double tol2 = a.tol * a.tol;
+    {
+        // Every cross pair (s, b + s2) of the block pair is the pivot of one
+        // inner step.  If none fails the skip test (2.3) on A_P as staged, the
+        // first step rotates nothing, A_P stays as it is, and by induction no
+        // step rotates: the whole solve is skipped (W = I).
+        int fails = 0;
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+            fails |= rel_orthogonal_sq(buf[s * kLd + s], buf[(kB + s2[q]) * kLd + kB + s2[q]], LR[q], a.tol, tol2)
+                         ? 0
+                         : 1;
+        if (__ballot(fails) != 0ull && lane == 0) atomicOr(&live, 1);
+    }
     const int nxt = (lane & 32) | ((lane + 1) & 31);  // lane of (d, s + 1), resp. W column s2 + 1
     double *const xlr = buf, *const xrl = buf + 2 * kB * kB;  // [2][b * b] each
     // pivots of slot s (lanes 0 .. b-1 of the first wave, q = 0)
@@ -541,11 +557,12 @@ __global__ __launch_bounds__(NT) void block_inner_cross_kernel(BlockArgsT<T> a)
     int code = 0, nrot = 0, nskip = 0, rank = 0;
     double maxt = 0.0;
     unsigned long long tmask = 0ull;  // local columns touched by a rotation (first wave)
-    const double tol2 = a.tol * a.tol;
     if (tid < 64) __builtin_amdgcn_s_setprio(2);
     __syncthreads();
+    const int nsteps = live ? kB : 0;  // the same in every thread
+    if (nsteps == 0 && tid < kB) nskip = kB;
 
-    for (int u = 0; u < kB; ++u) {
+    for (int u = 0; u < nsteps; ++u) {
         const int pb = u & 1;
         if (tid < kB) {
             // skip test and rotation evaluated side by side (independent
