@@ -38,14 +38,14 @@ MEASURED_TRAFFIC = {
     "mode": "mixed",
     "sources": ["paper_1008_1371_amd/csrc/block_kernels.hip", "paper_1008_1371_amd/csrc/api.hip",
                 "paper_1008_1371_amd/csrc/internal.h"],
-    "sha256": "5bf6270326dbee49a21c80a9ccd2884d504269736118fbf90ca6dc413dbcf5ca",
+    "sha256": "c453457c0789181cdd49ac67cce794b4da3230dfd864a16c9deffd4dd850ce0a",
     "bytes_per_launch": {
-        "block_gram_kernel<float>": (32870.3 * 2.0 + 5120.0 * 1.0) * 1024,
-        "block_inner_kernel<float>": (22199.3 * 2.0 + 37637.4 * 1.0) * 1024,
-        "block_update_kernel<float>": (18689.0 * 2.0 + 36634.1 * 1.0) * 1024,
-        "block_gram_kernel<double>": (65598.5 * 2.0 + 10240.0 * 1.0) * 1024,
-        "block_inner_kernel<double>": (25059.6 * 2.0 + 37512.3 * 1.0) * 1024,
-        "block_update_kernel<double>": (18362.6 * 2.0 + 35535.0 * 1.0) * 1024,
+        "block_gram_kernel<float>": (32872.7 * 2.0 + 5120.0 * 1.0) * 1024,
+        "block_inner_kernel<float>": (22211.6 * 2.0 + 37782.1 * 1.0) * 1024,
+        "block_update_kernel<float>": (18693.7 * 2.0 + 36645.5 * 1.0) * 1024,
+        "block_gram_kernel<double>": (65598.6 * 2.0 + 10240.0 * 1.0) * 1024,
+        "block_inner_kernel<double>": (25036.2 * 2.0 + 37512.4 * 1.0) * 1024,
+        "block_update_kernel<double>": (18354.9 * 2.0 + 35535.0 * 1.0) * 1024,
     },
 }
 

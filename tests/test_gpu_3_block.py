@@ -130,3 +130,25 @@ def test_autotune_choice_used_and_cached(hsvd_ctx, tmp_path, monkeypatch):
         assert res2["info"]["block"] == res["info"]["block"]
         for k in ("sigma", "U", "V"):
             assert np.array_equal(res[k], res2[k])
+
+
+@pytest.mark.parametrize("mixed_pair", [False, True])
+def test_block_orthogonal_columns(hsvd_ctx, mixed_pair):
+    """Columns orthogonal to rounding: every pair passes the skip test (2.3),
+    so one sweep with no rotation ends the solve and the whole-launch skip of
+    the inner solve is taken by every block pair.  With one pair of columns
+    from different blocks mixed, that block pair rotates while the others in
+    the same launches skip.  Counts and results against the oracle."""
+    n, p = 256, 100
+    G = W.haar(n, seed=5) * np.logspace(0.0, -3.0, n)[None, :]
+    if mixed_pair:
+        G[:, [3, 70]] = G[:, [3, 70]] @ np.array([[1.0, 0.3], [0.2, 1.0]])
+    ref = oracle.hsvd(G, p, block=B)
+    res = run_lib(hsvd_ctx, G, p, algo=2)
+    say("orthogonal columns, mixed pair", mixed_pair, "rotations lib/orc", res["info"]["rotations"],
+        ref["rotations"], "sweeps", res["info"]["sweeps"], ref["sweeps"])
+    _gate(G, p, res, ref)
+    assert res["info"]["rotations"] == ref["rotations"] and res["info"]["skips"] == ref["skips"]
+    assert res["info"]["sweeps"] == ref["sweeps"]
+    if not mixed_pair:
+        assert ref["rotations"] == 0 and res["info"]["sweeps"] == 1
