@@ -419,6 +419,31 @@ __global__ __launch_bounds__(1024) void block_inner_circle_kernel(BlockArgsT<T> 
     }
 }
 
+// Per-slot rotation of the cross kernel in the precision its blocks are held
+// in: (t, c) with c negated for an applied trigonometric rotation, decoded to
+// (t, |c|, h) with h = -t for such a rotation, h = t otherwise.
+template <typename C>
+struct SlotRot;
+template <>
+struct SlotRot<float> {
+    typedef float2 packed;
+    static __device__ __forceinline__ float2 pack(double t, double c) { return make_float2((float)t, (float)c); }
+};
+template <>
+struct SlotRot<double> {
+    typedef double2 packed;
+    static __device__ __forceinline__ double2 pack(double t, double c) { return make_double2(t, c); }
+};
+template <typename C>
+struct Rot3 {
+    C x, y, z;  // t, |c|, h
+};
+template <typename C, typename P>
+__device__ __forceinline__ Rot3<C> unpack_rot(P r)
+{
+    return Rot3<C>{r.x, fabs(r.y), r.y < C(0) ? -r.x : r.x};
+}
+
 // ---------------------------------------------------------------------------
 // Inner solve of one block pair for the cross steps (every outer step but the
 // first of a sweep), register-resident.
@@ -454,9 +479,12 @@ __global__ __launch_bounds__(NT) void block_inner_cross_kernel(BlockArgsT<T> a)
     // A_P staging at the start, the two LR / RL exchange buffers in the loop
     __shared__ double buf[kB2 * kLd];
     // per slot (t, c), c negated for an applied trigonometric rotation (whose
-    // h is -t; otherwise h = t): 16 bytes per read, the LDS reads being the
-    // bulk of an inner step
-    __shared__ double2 prm[2][kB];
+    // h is -t; otherwise h = t): one read per slot and step, the LDS reads
+    // being the bulk of an inner step.  The blocks of A_P and W are held in
+    // the storage precision T: FP32 in the FP32 sweeps, where the rotations
+    // are still computed in FP64 from the FP32 pivots and applied in FP32
+    // (W is rounded to T on output in any case).
+    __shared__ typename SlotRot<T>::packed prm[2][kB];
     __shared__ int rotf[2][kB];  // slot rotated (read by the diagonal blocks)
     __shared__ int live;         // some cross pair fails the skip test
     if constexpr (NT == kB * kB) {
@@ -511,8 +539,8 @@ __global__ __launch_bounds__(NT) void block_inner_cross_kernel(BlockArgsT<T> a)
     __syncthreads();
     const int s = tid & 31;
     const int s1 = s;
-    double LL[K], LR[K], RL[K], RR[K];
-    double W0L[K], W0R[K], W1L[K], W1R[K];
+    T LL[K], LR[K], RL[K], RR[K];
+    T W0L[K], W0R[K], W1L[K], W1R[K];
     int s2[K], lr_cell[K], rl_cell[K];
     bool cf[K];
 #pragma unroll
@@ -522,16 +550,16 @@ __global__ __launch_bounds__(NT) void block_inner_cross_kernel(BlockArgsT<T> a)
         s2[q] = (s + d) & 31;
         cf[q] = s1 <= s2[q];
         // entry (x, y) is read at (min, max) for both mirror positions
-        LL[q] = buf[min(s1, s2[q]) * kLd + max(s1, s2[q])];
-        LR[q] = buf[s1 * kLd + kB + s2[q]];
-        RL[q] = buf[s2[q] * kLd + kB + s1];
-        RR[q] = buf[(kB + min(s1, s2[q])) * kLd + kB + max(s1, s2[q])];
+        LL[q] = (T)buf[min(s1, s2[q]) * kLd + max(s1, s2[q])];
+        LR[q] = (T)buf[s1 * kLd + kB + s2[q]];
+        RL[q] = (T)buf[s2[q] * kLd + kB + s1];
+        RR[q] = (T)buf[(kB + min(s1, s2[q])) * kLd + kB + max(s1, s2[q])];
         // W block of this position: rows {w1, b + w1} (w1 = d) by columns
         // {L_w2, R_w2} (w2 = s)
-        W0L[q] = d == s ? 1.0 : 0.0;
-        W0R[q] = 0.0;
-        W1L[q] = 0.0;
-        W1R[q] = d == s ? 1.0 : 0.0;
+        W0L[q] = d == s ? T(1) : T(0);
+        W0R[q] = T(0);
+        W1L[q] = T(0);
+        W1R[q] = d == s ? T(1) : T(0);
         lr_cell[q] = (((d + 1) & 31) << 5) | s;             // position (d + 1, s)
         rl_cell[q] = (((d + 31) & 31) << 5) | ((s + 1) & 31);  // position (d - 1, s + 1)
     }
@@ -541,19 +569,21 @@ __global__ __launch_bounds__(NT) void block_inner_cross_kernel(BlockArgsT<T> a)
         // Every cross pair (s, b + s2) of the block pair is the pivot of one
         // inner step.  If none fails the skip test (2.3) on A_P as staged, the
         // first step rotates nothing, A_P stays as it is, and by induction no
-        // step rotates: the whole solve is skipped (W = I).
+        // step rotates: the whole solve is skipped (W = I).  The test takes the
+        // entries as the loop holds them (rounded to T).
         int fails = 0;
 #pragma unroll
         for (int q = 0; q < K; ++q)
-            fails |= rel_orthogonal_sq(buf[s * kLd + s], buf[(kB + s2[q]) * kLd + kB + s2[q]], LR[q], a.tol, tol2)
+            fails |= rel_orthogonal_sq((T)buf[s * kLd + s], (T)buf[(kB + s2[q]) * kLd + kB + s2[q]], LR[q], a.tol,
+                                       tol2)
                          ? 0
                          : 1;
         if (__ballot(fails) != 0ull && lane == 0) atomicOr(&live, 1);
     }
     const int nxt = (lane & 32) | ((lane + 1) & 31);  // lane of (d, s + 1), resp. W column s2 + 1
-    double *const xlr = buf, *const xrl = buf + 2 * kB * kB;  // [2][b * b] each
+    T *const xlr = reinterpret_cast<T *>(buf), *const xrl = xlr + 2 * kB * kB;  // [2][b * b] each
     // pivots of slot s (lanes 0 .. b-1 of the first wave, q = 0)
-    double pll = LL[0], plr = LR[0], prr = RR[0];
+    T pll = LL[0], plr = LR[0], prr = RR[0];
     int code = 0, nrot = 0, nskip = 0, rank = 0;
     double maxt = 0.0;
     unsigned long long tmask = 0ull;  // local columns touched by a rotation (first wave)
@@ -588,14 +618,13 @@ __global__ __launch_bounds__(NT) void block_inner_cross_kernel(BlockArgsT<T> a)
                 maxt = fmax(maxt, fabs(t));
                 tmask |= (1ull << s) | (1ull << (kB + ((s + u) & 31)));
             }
-            prm[pb][s] = make_double2(t, (rot && hyp < 0) ? -c : c);
+            prm[pb][s] = SlotRot<T>::pack(t, (rot && hyp < 0) ? -c : c);
             rotf[pb][s] = rot;
         }
         __syncthreads();
         // slot s1 = s is common to the thread's positions; W's column slot
         // w2 is s1.  (t, c, h) with h = -t for a trigonometric rotation
-        const double2 r1 = prm[pb][s1];
-        const double3 p1 = make_double3(r1.x, fabs(r1.y), r1.y < 0.0 ? -r1.x : r1.x);
+        const Rot3<T> p1 = unpack_rot<T>(prm[pb][s1]);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             if (u > 0) {
@@ -603,26 +632,25 @@ __global__ __launch_bounds__(NT) void block_inner_cross_kernel(BlockArgsT<T> a)
                 LR[q] = xlr[(pb ^ 1) * (kB * kB) + lr_cell[q]];
                 RL[q] = xrl[(pb ^ 1) * (kB * kB) + rl_cell[q]];
             }
-            const double2 r2 = prm[pb][s2[q]];
-            const double3 p2 = make_double3(r2.x, fabs(r2.y), r2.y < 0.0 ? -r2.x : r2.x);
+            const Rot3<T> p2 = unpack_rot<T>(prm[pb][s2[q]]);
             // A block, rows by slot s1, columns by slot s2.  Columns first iff
             // s1 <= s2; otherwise the same column-then-row sequence runs on
             // the transposed block with the slots exchanged, which is the
             // row-then-column order on the block itself.
-            const double3 pa = cf[q] ? p2 : p1, pq = cf[q] ? p1 : p2;
-            const double x01 = cf[q] ? LR[q] : RL[q], x10 = cf[q] ? RL[q] : LR[q];
-            const double f00 = fma(pa.z, x01, LL[q]) * pa.y, f01 = fma(pa.x, LL[q], x01) * pa.y;
-            const double f10 = fma(pa.z, RR[q], x10) * pa.y, f11 = fma(pa.x, x10, RR[q]) * pa.y;
-            const double y00 = fma(pq.z, f10, f00) * pq.y, y10 = fma(pq.x, f00, f10) * pq.y;
-            const double y01 = fma(pq.z, f11, f01) * pq.y, y11 = fma(pq.x, f01, f11) * pq.y;
+            const Rot3<T> pa = cf[q] ? p2 : p1, pq = cf[q] ? p1 : p2;
+            const T x01 = cf[q] ? LR[q] : RL[q], x10 = cf[q] ? RL[q] : LR[q];
+            const T f00 = fma(pa.z, x01, LL[q]) * pa.y, f01 = fma(pa.x, LL[q], x01) * pa.y;
+            const T f10 = fma(pa.z, RR[q], x10) * pa.y, f11 = fma(pa.x, x10, RR[q]) * pa.y;
+            const T y00 = fma(pq.z, f10, f00) * pq.y, y10 = fma(pq.x, f00, f10) * pq.y;
+            const T y01 = fma(pq.z, f11, f01) * pq.y, y11 = fma(pq.x, f01, f11) * pq.y;
             LL[q] = y00;
             RR[q] = y11;
             LR[q] = cf[q] ? y01 : y10;
             RL[q] = cf[q] ? y10 : y01;
         }
         if (diag && rotf[pb][s1]) {
-            LR[0] = 0.0;
-            RL[0] = 0.0;
+            LR[0] = T(0);
+            RL[0] = T(0);
         }
         if (u + 1 < kB) {
 #pragma unroll
@@ -642,9 +670,9 @@ __global__ __launch_bounds__(NT) void block_inner_cross_kernel(BlockArgsT<T> a)
         // W <- W R on columns (L_w2, R_w2), then the shift of its R half
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            const double3 pw = p1;
-            const double a0 = fma(pw.z, W0R[q], W0L[q]) * pw.y, b0 = fma(pw.x, W0L[q], W0R[q]) * pw.y;
-            const double a1 = fma(pw.z, W1R[q], W1L[q]) * pw.y, b1 = fma(pw.x, W1L[q], W1R[q]) * pw.y;
+            const Rot3<T> pw = p1;
+            const T a0 = fma(pw.z, W0R[q], W0L[q]) * pw.y, b0 = fma(pw.x, W0L[q], W0R[q]) * pw.y;
+            const T a1 = fma(pw.z, W1R[q], W1L[q]) * pw.y, b1 = fma(pw.x, W1L[q], W1R[q]) * pw.y;
             W0L[q] = a0;
             W1L[q] = a1;
             W0R[q] = __shfl(b0, nxt, 64);
