@@ -38,14 +38,14 @@ MEASURED_TRAFFIC = {
     "mode": "mixed",
     "sources": ["paper_1008_1371_amd/csrc/block_kernels.hip", "paper_1008_1371_amd/csrc/api.hip",
                 "paper_1008_1371_amd/csrc/internal.h"],
-    "sha256": "c453457c0789181cdd49ac67cce794b4da3230dfd864a16c9deffd4dd850ce0a",
+    "sha256": "65f8490671b1d70431ef341be2e09d3f5821553fa2c13ca207732ee78b3e85c0",
     "bytes_per_launch": {
-        "block_gram_kernel<float>": (32872.7 * 2.0 + 5120.0 * 1.0) * 1024,
-        "block_inner_kernel<float>": (22211.6 * 2.0 + 37782.1 * 1.0) * 1024,
-        "block_update_kernel<float>": (18693.7 * 2.0 + 36645.5 * 1.0) * 1024,
-        "block_gram_kernel<double>": (65598.6 * 2.0 + 10240.0 * 1.0) * 1024,
-        "block_inner_kernel<double>": (25036.2 * 2.0 + 37512.4 * 1.0) * 1024,
-        "block_update_kernel<double>": (18354.9 * 2.0 + 35535.0 * 1.0) * 1024,
+        "block_gram_kernel<float>": (32866.6 * 2.0 + 5120.0 * 1.0) * 1024,
+        "block_inner_kernel<float>": (22137.3 * 2.0 + 37627.1 * 1.0) * 1024,
+        "block_update_kernel<float>": (18688.0 * 2.0 + 36674.5 * 1.0) * 1024,
+        "block_gram_kernel<double>": (65598.5 * 2.0 + 10240.0 * 1.0) * 1024,
+        "block_inner_kernel<double>": (25032.9 * 2.0 + 37493.6 * 1.0) * 1024,
+        "block_update_kernel<double>": (18354.2 * 2.0 + 35512.8 * 1.0) * 1024,
     },
 }
 
