@@ -69,3 +69,26 @@ def test_mixed_full_size_graded4096(hsvd_ctx):
     say("mixed 4096", {k: res["info"][k] for k in ("sweeps_fp32", "sweeps", "reorth_iters",
                                                    "reorth_resid", "ms_total")})
     pins.check_invariants(G, p, res, tol=1e-15 * 4096)
+
+
+@pytest.mark.parametrize("mixed_pair", [False, True])
+def test_mixed_orthogonal_columns(hsvd_ctx, mixed_pair):
+    """Columns orthogonal to FP64 rounding, and the same with one pair of
+    columns from different blocks mixed: the FP32 sweeps see these through the
+    rounding of G to FP32, so whole launches of the inner solve are skipped
+    while some pairs still rotate; the FP64 refinement then decides.  Result
+    against the oracle."""
+    n, p = 256, 100
+    G = W.haar(n, seed=5) * np.logspace(0.0, -3.0, n)[None, :]
+    if mixed_pair:
+        G[:, [3, 70]] = G[:, [3, 70]] @ np.array([[1.0, 0.3], [0.2, 1.0]])
+    spread, ref = ordering_spread(G, p, block=32)
+    res = _mixed(hsvd_ctx, G, p)
+    assert res["status"] == 0, res["status"]
+    e = compare(res, ref, p)
+    say("mixed orthogonal columns", mixed_pair, e, "fp32/fp64 sweeps", res["info"]["sweeps_fp32"],
+        res["info"]["sweeps"], "rotations", res["info"]["rotations"], "ordering spread", spread)
+    assert e["sigma_norm"] <= 1e-12
+    gate = max(1e-12, 10 * max(spread["U"], spread["V"]))
+    assert e["U"] <= gate and e["V"] <= gate, e
+    pins.check_invariants(G, p, res, tol=ref["tol"])
