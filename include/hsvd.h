@@ -77,7 +77,8 @@ enum {
     HSVD_K_BLOCK_INNER = 2,    /* block path, FP64: inner rotations of each block pair     */
     HSVD_K_BLOCK_UPDATE = 3,   /* block path, FP64: [G_P | V_P] <- [G_P | V_P] W           */
     HSVD_K_BLOCK_GRAM32 = 4,   /* mixed path, FP32 sweeps: Gram on FP32 MFMA               */
-    HSVD_K_BLOCK_INNER32 = 5,  /* mixed path, FP32 sweeps: inner rotations (FP64)          */
+    HSVD_K_BLOCK_INNER32 = 5,  /* mixed path, FP32 sweeps: inner rotations, parameters in   */
+                               /* FP64, applied to the FP32-held blocks                     */
     HSVD_K_BLOCK_UPDATE32 = 6, /* mixed path, FP32 sweeps: update on FP32 MFMA             */
     HSVD_K_REORTH = 7,         /* mixed path: J-re-orthogonalisation of V and G1 = G X     */
     HSVD_NKERNELS = 8
