@@ -45,8 +45,11 @@ typedef enum { HSVD_ORD_MODMOD = 0, HSVD_ORD_ROUNDROBIN = 1 } hsvd_ordering;
 
 typedef struct {
     int precision;   /* hsvd_precision: HSVD_FP64, or HSVD_MIXED = FP32 block sweeps on
-                        FP32 MFMA until the largest tangent stagnates, FP64
-                        J-re-orthogonalisation of V, then FP64 block sweeps          */
+                        FP32 MFMA until they stop paying (switch rule of the design
+                        notes), FP64 J-re-orthogonalisation of V, then FP64 block
+                        sweeps.  If an FP32 sweep flags a pair as rank deficient, or
+                        the re-orthogonalisation ends above reorth_accept, the solve
+                        starts again from G in FP64 (hsvd_info.fp64_restart)           */
     int algo;        /* hsvd_algo                                                        */
     int ordering;    /* hsvd_ordering: modified modulus (Sec. 2, Algs. 4.3-4.4) or the
                         round-robin circle method starting on the same antidiagonal      */
@@ -68,6 +71,9 @@ typedef struct {
                         pointwise method over its 2b columns until one rotates nothing, at
                         most k.  k > 0 makes HSVD_AUTO take the block path; the pairwise
                         path rejects k > 0 with HSVD_E_INVAL                           */
+    double reorth_accept; /* mixed path: largest accepted max |J X^T J X - I| after the
+                        Newton-Schulz J-re-orthogonalisation of V (above it the
+                        solve restarts from G in FP64); <= 0: 16384 n u, u = 2^-53  */
 } hsvd_params;
 
 /* Kernel classes timed in hsvd_info (index into the kernel_* arrays). */
@@ -81,6 +87,7 @@ enum {
                                /* FP64, applied to the FP32-held blocks                     */
     HSVD_K_BLOCK_UPDATE32 = 6, /* mixed path, FP32 sweeps: update on FP32 MFMA             */
     HSVD_K_REORTH = 7,         /* mixed path: J-re-orthogonalisation of V and G1 = G X     */
+                               /* (FP64 MFMA products, gemm_kernels)                       */
     HSVD_NKERNELS = 8
 };
 
@@ -95,6 +102,10 @@ typedef struct {
     int reorth_iters;        /* mixed path: Newton-Schulz iterations on V                */
     double max_t_last;       /* largest |t| of the last sweep                            */
     double reorth_resid;     /* mixed path: final max |J X^T J X - I|                    */
+    int fp64_restart;        /* mixed path: 1 when the FP32 phase was abandoned and the
+                                solve ran again in FP64 from G (rank flag in an FP32
+                                sweep, or reorth_resid above reorth_accept)            */
+    int pad_;
     long long rotations;     /* rotations applied                                        */
     long long skips;         /* pair visits skipped by eq. (2.3)                         */
     long long steps;         /* parallel (outer) steps executed                          */
@@ -125,7 +136,14 @@ void hsvd_default_params(hsvd_params *prm);
 
 /* One-sided Jacobi HSVD of a square G (Sec. 2 and Sec. 4, Algs. 4.1-4.5).
  *   G       device, n x n, leading dimension lda >= n; read only (copied).
- *   n, p    order and number of +1 signs in J (0 <= p <= n); J = diag(I_p, -I_{n-p}).
+ *   jsig    device, n signed chars (+1 or -1): J's diagonal in the column
+ *           order of G, with exactly p entries +1 in any order; or NULL for
+ *           J = diag(I_p, -I_{n-p}).  A signature that is not already in that
+ *           canonical order is handled by stably partitioning the columns (+1
+ *           first), solving, and mapping the outputs back to the input column
+ *           order (V = P V_p P^T, so G V = U Sigma and V^T J V = J with the
+ *           caller's J); this copies G once more and reads jsig to the host.
+ *   n, p    order and number of +1 signs in J (0 <= p <= n).
  *   prm     host; NULL = defaults.
  * Outputs (device, caller-allocated; any may be NULL except sigma):
  *   sigma[n]   hyperbolic singular values, physical (input) column order.
@@ -136,46 +154,40 @@ void hsvd_default_params(hsvd_params *prm);
  *   perm[n]    physical column index by final sorted position (rho of Fig. 4.1).
  *   info       host; may be NULL.
  * Odd n is bordered by a unit column with a negative sign (eq. 4.1); the
- * border never appears in the outputs.  Errors: see hsvd_status. */
-hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p,
-                       const hsvd_params *prm, double *sigma, double *U, int ldu,
-                       double *V, int ldv, double *lambda, int *perm, hsvd_info *info);
-
-/* As hsvd_solve for a signature given in any order: jsig (device, n signed
- * chars, each +1 or -1) is J's diagonal in the column order of G.  The columns
- * are stably partitioned (+1 first), solved, and the outputs mapped back:
- * sigma, U columns and lambda in the input column order, V = P V_p P^T (so
- * G V = U Sigma and V^T J V = J with this J), perm as physical input columns.
- * Errors: HSVD_E_INVAL also for an entry other than +-1.  Synchronises. */
-hsvd_status hsvd_solve_j(hsvd_ctx *ctx, const double *G, int lda, int n, const signed char *jsig,
-                         const hsvd_params *prm, double *sigma, double *U, int ldu, double *V, int ldv,
-                         double *lambda, int *perm, hsvd_info *info);
+ * border never appears in the outputs.  Errors: see hsvd_status; HSVD_E_INVAL
+ * also for a jsig entry other than +-1 or a count of +1 entries other than p.
+ * Synchronises with the context's stream before returning. */
+hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, const signed char *jsig, int n, int p,
+                       const hsvd_params *prm, double *sigma, double *U, int ldu, double *V, int ldv,
+                       double *lambda, int *perm, hsvd_info *info);
 
 /* Batched solves: `batch` independent problems G_k (n[k] x n[k], 1 <= n[k] <= 1024,
  * J_k = diag(I_p[k], -I_{n[k]-p[k]})), each solved as by hsvd_solve with the block
  * path and its own tolerance (prm->tol <= 0: 1e-15 n[k]) and stop rule, in FP64
  * or (prm->precision = HSVD_MIXED) with FP32 sweeps first, each problem leaving
  * them by its own switch rule, then the J-re-orthogonalisation of its V and
- * FP64 refinement sweeps.
- *   n, p, off, voff  host arrays of `batch` entries: order, number of +1 signs,
- *                    element offset of G_k / U_k / V_k in the packed matrices
- *                    (column-major, leading dimension n[k]), element offset of
- *                    sigma_k / lambda_k in the packed vectors.
+ * FP64 refinement sweeps (or, per problem, the FP64 restart of hsvd_solve).
+ *   n, p, off, voff  device (or host) arrays of `batch` entries: order, number of
+ *                    +1 signs, element offset of G_k / U_k / V_k in the packed
+ *                    matrices (column-major, leading dimension n[k]), element
+ *                    offset of sigma_k / lambda_k in the packed vectors.  The
+ *                    library reads them to the host once, to plan the launches.
  *   G                device, packed inputs (read only).
  *   sigma, U, V, lambda  device, packed outputs (U, V, lambda may be NULL;
  *                    V requires prm->want_v).
- *   status, sweeps   host arrays of `batch` ints (may be NULL): each problem's
- *                    hsvd_status and sweep count.
- *   info             host, may be NULL: totals over the batch (sweeps and
- *                    sweeps_fp32 = largest; per-problem sweeps are FP64 sweeps).
+ *   info             device or host array of `batch` hsvd_info, or NULL: per
+ *                    problem status, sweeps (FP64), sweeps_fp32, code, r, block,
+ *                    ldg, reorth_iters, reorth_resid, fp64_restart, rotations,
+ *                    skips, active_pairs; ms_total is the device time of the
+ *                    whole batched call; the kernel_* arrays are zero.
  * Problems are grouped by their bordered order (a multiple of 2b); each group
- * runs as one sequence of launches that covers all of its problems.  Returns
- * HSVD_OK when every problem converged, else the status of the first problem
- * that did not.  Synchronises. */
+ * runs as one sequence of launches that covers all of its problems, with the
+ * stop rule decided per problem on the device.  Returns HSVD_OK when every
+ * problem converged, else the status of the first problem that did not.
+ * Synchronises. */
 hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n, const int *p, const long long *off,
                                const long long *voff, const double *G, const hsvd_params *prm, double *sigma,
-                               double *U, double *V, double *lambda, int *status, int *sweeps,
-                               hsvd_info *info);
+                               double *U, double *V, double *lambda, hsvd_info *info);
 
 /* Autotuner.  Times the speed-only choices of the library on a seeded synthetic
  * problem of order n (uniform entries in [-1, 1) from a counter-based hash,

@@ -13,8 +13,6 @@
 #include <new>
 #include <vector>
 
-#include <rocblas/rocblas.h>
-
 #include "internal.h"
 
 struct hsvd_ctx {
@@ -26,7 +24,6 @@ struct hsvd_ctx {
     size_t aux_bytes = 0;
     hsvd::Ctl *host_ctl = nullptr;           // pinned
     std::vector<hipEvent_t> events;          // reusable timing events
-    rocblas_handle blas = nullptr;           // created on the first mixed solve
     hipStream_t cap = nullptr;               // non-blocking stream for graph capture (default priority)
     hipEvent_t join = nullptr;               // orders the capture stream with the caller's stream
     struct Tune {
@@ -261,7 +258,6 @@ hsvd_status hsvd_destroy(hsvd_ctx *ctx)
     if (ctx->ws) hipFree(ctx->ws);
     if (ctx->aux) hipFree(ctx->aux);
     if (ctx->host_ctl) hipHostFree(ctx->host_ctl);
-    if (ctx->blas) rocblas_destroy_handle(ctx->blas);
     if (ctx->cap) hipStreamDestroy(ctx->cap);
     if (ctx->join) hipEventDestroy(ctx->join);
     delete ctx;
@@ -347,11 +343,13 @@ template <typename T, typename Done>
 hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, const T *Gcur, int pairs,
                          int steps_per_sweep, int max_sweeps, bool sort, int r, int p, int ldg, long long &gstep,
                          int kbase, double *kms, long long *klaunch, long long *ktimed, int &sweeps,
-                         long long &steps, SweepResult &last, bool &finished, Done done)
+                         long long &steps, SweepResult &last, bool &finished, bool timing, Done done)
 {
     hipStream_t st = ctx->stream;
-    hipEvent_t *ev = ctx->events.data();
-    hipEvent_t *evv = ev + 4 + 4 * steps_per_sweep;  // around the V update of a sweep's last step
+    // timing: event pairs around sampled launches (the events exist; see
+    // ensure_events); otherwise no event is recorded
+    hipEvent_t *ev = timing ? ctx->events.data() : nullptr;
+    hipEvent_t *evv = timing ? ev + 4 + 4 * steps_per_sweep : nullptr;  // around the V update of a sweep's last step
     finished = false;
     // W and the masks alternate between two buffers by step parity.  With V
     // accumulated by the block-oriented method, the V half of a step's update
@@ -383,8 +381,8 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
                 ba.S_prev = w.S2 + (par ^ 1) * pairs;  // the previous step's S_in: rewritten by this step's update
                 ba.step_prev = k - 1;
             }
-            hipEvent_t *e = ev + 4 + 4 * k;
-            const bool tm = k % kTimeEvery == 0;
+            hipEvent_t *e = timing ? ev + 4 + 4 * k : nullptr;
+            const bool tm = timing && k % kTimeEvery == 0;
             if (tm) HSVD_TRY(hipEventRecord(e[0], st));
             HSVD_TRY(launch_block_gram<T>(st, ba));
             if (tm) HSVD_TRY(hipEventRecord(e[1], st));
@@ -401,9 +399,9 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
             lv.W = Wb + par * wstride;
             lv.active = Ab + par * pairs;
             lv.vprev_wgs = 0;
-            HSVD_TRY(hipEventRecord(evv[0], st));
+            if (timing) HSVD_TRY(hipEventRecord(evv[0], st));
             HSVD_TRY(launch_block_update<T>(st, lv, UPD_V));
-            HSVD_TRY(hipEventRecord(evv[1], st));
+            if (timing) HSVD_TRY(hipEventRecord(evv[1], st));
         }
         for (int q = 0; q < 3; ++q) klaunch[kbase + q] += steps_per_sweep;
         // the kept diagonal: fresh column norms of the updated columns
@@ -413,7 +411,7 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
         HSVD_TRY(launch_sweep_reduce(st, w, pairs));
         HSVD_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
         HSVD_TRY(hipStreamSynchronize(st));
-        {
+        if (timing) {
             double first[3] = {0.0, 0.0, 0.0}, rest[3] = {0.0, 0.0, 0.0};
             int nrest = 0;
             for (int k = 0; k < steps_per_sweep; k += kTimeEvery) {
@@ -435,9 +433,9 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
                 HSVD_TRY(hipEventElapsedTime(&ms, evv[0], evv[1]));
                 kms[kbase + 2] += ms;
                 ktimed[kbase + 2] += 1;
-                klaunch[kbase + 2] += 1;
             }
         }
+        if (fuse) klaunch[kbase + 2] += 1;
         ++sweeps;
         last.code = ctx->host_ctl->code;
         last.maxt = ctx->host_ctl->maxt;
@@ -463,22 +461,16 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
     return HSVD_OK;
 }
 
-#define BLAS_TRY(expr)                                          \
-    do {                                                        \
-        if ((expr) != rocblas_status_success) return HSVD_E_DEVICE; \
-    } while (0)
-
 // Newton-Schulz J-re-orthogonalisation of X (in w.V, FP64, promoted from the
-// FP32 sweeps) followed by G <- G X.  Uses w.T1, w.T2.
+// FP32 sweeps), X <- X (3I - J X^T J X) / 2, followed by G <- G X.  The
+// products run on the library's FP64 MFMA kernels (X^T J X as a symmetric
+// product with J applied to the rows of the second operand as it is loaded).
+// Uses w.T1, w.T2.  iters: corrections applied; resid: max |J X^T J X - I| of
+// the final X.  With gx = false G is left alone.
 hsvd_status reorthogonalise(hsvd_ctx *ctx, const Workspace &w, int n, int r, int p, int ldg, int &iters,
-                            double &resid)
+                            double &resid, bool gx = true)
 {
     hipStream_t st = ctx->stream;
-    if (!ctx->blas) {
-        if (rocblas_create_handle(&ctx->blas) != rocblas_status_success) return HSVD_E_DEVICE;
-    }
-    BLAS_TRY(rocblas_set_stream(ctx->blas, st));
-    const double one = 1.0, zero = 0.0;
     iters = 0;
     resid = 1.0;
     double prev = 2.0;
@@ -486,10 +478,18 @@ hsvd_status reorthogonalise(hsvd_ctx *ctx, const Workspace &w, int n, int r, int
     // n real columns (the bordering columns are exact unit vectors and add
     // no rounding)
     const double floor_ = 16.0 * n * 0x1p-53;
-    for (int it = 0; it < 6; ++it) {
-        HSVD_TRY(launch_rowsign(st, w.V, w.T1, p, ldg, r));  // T1 = J X
-        BLAS_TRY(rocblas_dgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, r, r, r, &one, w.V,
-                               ldg, w.T1, ldg, &zero, w.T2, ldg));  // T2 = X^T J X
+    GemmArgs sy;  // T2 = X^T J X
+    sy.A = w.V;
+    sy.B = w.V;
+    sy.C = w.T2;
+    sy.M = sy.N = sy.K = r;
+    sy.lda = sy.ldb = sy.ldc = ldg;
+    sy.p = p;
+    GemmArgs xt = sy;  // T1 = X T2
+    xt.B = w.T2;
+    xt.C = w.T1;
+    for (int it = 0; it <= 6; ++it) {
+        HSVD_TRY(launch_gemm(st, sy, 1, true, true, true));
         ctx->host_ctl->nsres = 0.0;
         HSVD_TRY(hipMemcpyAsync(&w.ctl->nsres, &ctx->host_ctl->nsres, sizeof(double), hipMemcpyHostToDevice, st));
         HSVD_TRY(launch_ns_form(st, w.T2, p, ldg, r, w.ctl));  // T2 = (3I - J X^T J X) / 2
@@ -497,34 +497,51 @@ hsvd_status reorthogonalise(hsvd_ctx *ctx, const Workspace &w, int n, int r, int
         HSVD_TRY(hipStreamSynchronize(st));
         resid = ctx->host_ctl->nsres;
         // stop once X is J-orthogonal to working accuracy (residual at the
-        // rounding floor, or no longer falling quadratically) -- that last
-        // correction is not applied
-        if (!(resid < 1.0) || resid <= floor_ || (iters > 0 && resid > 0.25 * prev)) break;
-        BLAS_TRY(rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, r, r, r, &one, w.V, ldg,
-                               w.T2, ldg, &zero, w.T1, ldg));  // T1 = X T2
+        // rounding floor, or no longer falling quadratically; or after six
+        // corrections) -- that last correction is not applied; the caller
+        // judges the final residual
+        if (it == 6 || !(resid < 1.0) || resid <= floor_ || (iters > 0 && resid > 0.25 * prev)) break;
+        HSVD_TRY(launch_gemm(st, xt, 1, false, false, false));
         HSVD_TRY(launch_copy(st, w.T1, w.V, ldg, r));
         ++iters;
         prev = resid;
     }
-    BLAS_TRY(rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, r, r, r, &one, w.G, ldg,
-                           w.V, ldg, &zero, w.T1, ldg));  // T1 = G X
-    HSVD_TRY(launch_copy(st, w.T1, w.G, ldg, r));
+    if (gx) {
+        GemmArgs g1 = sy;  // T1 = G X
+        g1.A = w.G;
+        g1.B = w.V;
+        g1.C = w.T1;
+        HSVD_TRY(launch_gemm(st, g1, 1, false, false, false));
+        HSVD_TRY(launch_copy(st, w.T1, w.G, ldg, r));
+    }
     return HSVD_OK;
+}
+
+// Largest accepted final residual of the J-re-orthogonalisation.
+double reorth_accept_bound(const hsvd_params &prm, int n)
+{
+    return prm.reorth_accept > 0.0 ? prm.reorth_accept : 16384.0 * n * 0x1p-53;
 }
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, const hsvd_params *prm_in,
-                       double *sigma, double *U, int ldu, double *V, int ldv, double *lambda, int *perm,
-                       hsvd_info *info)
+// Where a solve's workspace comes from, and what it may create.
+struct SolveMode {
+    void *ws = nullptr;   // nullptr: the context's workspace (allocated or grown on demand)
+    size_t ws_cap = 0;    // bytes available at ws
+    bool timing = true;   // HIP events around the solve and sampled kernels (events are created on demand)
+    bool graphs = true;   // prm.graph honoured (a captured graph is created per solve)
+};
+
+// hsvd_solve for J = diag(I_p, -I_{n-p}) (columns in canonical order).
+hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int p, const hsvd_params &prm,
+                            double *sigma, double *U, int ldu, double *V, int ldv, double *lambda, int *perm,
+                            hsvd_info *info, const SolveMode &mode)
 {
     if (info) memset(info, 0, sizeof(*info));
     if (!ctx || !G || !sigma) return HSVD_E_INVAL;
-    hsvd_params prm;
-    if (prm_in) prm = *prm_in;
-    else hsvd_default_params(&prm);
     if (n < 1 || p < 0 || p > n || lda < n) return HSVD_E_INVAL;
     if (U && ldu < n) return HSVD_E_INVAL;
     if (V && ldv < n) return HSVD_E_INVAL;
@@ -580,27 +597,45 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
     // the mixed path needs V (to re-orthogonalise and form G X) even when it is not returned
     const bool acc_v = want_v || mixed;
     const Layout L = make_layout(n, r, ldg, acc_v, pairs, splits, block ? 2 * b : 0, mixed);
-    hsvd_status s = ensure_ws(ctx, L.bytes);
-    if (s != HSVD_OK) return s;
-    const int nev = block ? 4 + 4 * steps_per_sweep + 2 : 4;
-    s = ensure_events(ctx, (size_t)nev);
-    if (s != HSVD_OK) return s;
-    const Workspace w = carve(ctx->ws, L);
+    hsvd_status s = HSVD_OK;
+    void *base = mode.ws;
+    if (base) {
+        if (L.bytes > mode.ws_cap) return HSVD_E_NOMEM;
+    } else {
+        s = ensure_ws(ctx, L.bytes);
+        if (s != HSVD_OK) return s;
+        base = ctx->ws;
+    }
+    const bool timing = mode.timing;
+    if (timing) {
+        const int nev = block ? 4 + 4 * steps_per_sweep + 2 : 4;
+        s = ensure_events(ctx, (size_t)nev);
+        if (s != HSVD_OK) return s;
+    }
+    const Workspace w = carve(base, L);
     hipStream_t st = ctx->stream;
-    hipEvent_t *ev = ctx->events.data();
+    hipEvent_t *ev = timing ? ctx->events.data() : nullptr;
 
-    HSVD_TRY(hipEventRecord(ev[0], st));
-    HSVD_TRY(launch_zero_ctl(st, w.ctl));
-    HSVD_TRY(launch_setup(st, G, lda, n, w, r, ldg, want_v));
-    HSVD_TRY(launch_precompute(st, w, r, ldg));
-    if (block) HSVD_TRY(launch_block_stepper_init(st, w.S2, nb));
-    if (prm.sort) HSVD_TRY(launch_sort(st, w.d, w.rho, w.dtmp, w.rtmp, r, p));
-    HSVD_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    HSVD_TRY(hipStreamSynchronize(st));
+    // set-up (Alg. 4.2): bordered working copy, V = I, d, rho, steppers, the
+    // first sort; the control block tells whether the input is usable
+    auto start = [&]() -> hsvd_status {
+        HSVD_TRY(launch_zero_ctl(st, w.ctl));
+        HSVD_TRY(launch_setup(st, G, lda, n, w, r, ldg, want_v));
+        HSVD_TRY(launch_precompute(st, w, r, ldg));
+        if (block) HSVD_TRY(launch_block_stepper_init(st, w.S2, nb));
+        if (prm.sort) HSVD_TRY(launch_sort(st, w.d, w.rho, w.dtmp, w.rtmp, r, p));
+        HSVD_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HSVD_TRY(hipStreamSynchronize(st));
+        return HSVD_OK;
+    };
+    if (timing) HSVD_TRY(hipEventRecord(ev[0], st));
+    s = start();
+    if (s != HSVD_OK) return s;
 
     hsvd_status status = HSVD_OK;
-    int sweeps = 0, sweeps32 = 0, code = 0, ns_iters = 0;
+    int sweeps = 0, sweeps32 = 0, code = 0, ns_iters = 0, restarted = 0;
     unsigned long long tcol32 = 0;  // touched columns of the FP32 phase (cumulative counter at its end)
+    unsigned long long tcol64_base = 0;  // cumulative counter where the FP64 sweeps start
     double maxt_last = 0.0, ns_resid = 0.0;
     long long steps = 0;
     double kms[HSVD_NKERNELS] = {0};
@@ -638,7 +673,8 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
         // stream before and after.
         SweepGraph sg(ctx, st);
         hipStream_t q = st;
-        if (prm.graph) {
+        const bool graph = prm.graph && mode.graphs;
+        if (graph) {
             HSVD_TRY(sg.begin(q));
             for (int k = 0; k < steps_per_sweep; ++k) {
                 a.step = k;
@@ -651,8 +687,8 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             HSVD_TRY(sg.end(q));
         }
         for (int sw = 0; sw < max_sweeps; ++sw) {
-            HSVD_TRY(hipEventRecord(ev[2], q));
-            if (prm.graph) {
+            if (timing) HSVD_TRY(hipEventRecord(ev[2], q));
+            if (graph) {
                 HSVD_TRY(hipGraphLaunch(sg.exec, q));
             } else {
                 for (int k = 0; k < steps_per_sweep; ++k) {
@@ -660,7 +696,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
                     HSVD_TRY(launch_pair_step(q, a));
                 }
             }
-            HSVD_TRY(hipEventRecord(ev[3], q));
+            if (timing) HSVD_TRY(hipEventRecord(ev[3], q));
             klaunch[HSVD_K_PAIR_STEP] += steps_per_sweep;
             ktimed[HSVD_K_PAIR_STEP] += steps_per_sweep;
             steps += steps_per_sweep;
@@ -668,9 +704,11 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             HSVD_TRY(launch_sweep_reduce(q, w, r / 2));
             HSVD_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, q));
             HSVD_TRY(hipStreamSynchronize(q));
-            float ms = 0.f;
-            HSVD_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
-            kms[HSVD_K_PAIR_STEP] += ms;
+            if (timing) {
+                float ms = 0.f;
+                HSVD_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
+                kms[HSVD_K_PAIR_STEP] += ms;
+            }
             ++sweeps;
             code = ctx->host_ctl->code;
             maxt_last = ctx->host_ctl->maxt;
@@ -743,24 +781,52 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             };
             status = block_sweeps<float>(ctx, w, fa, w.G32, pairs, steps_per_sweep, max_sweeps, prm.sort != 0, r,
                                          p, ldg, gstep, HSVD_K_BLOCK_GRAM32, kms, klaunch, ktimed, sw32, steps, last,
-                                         finished, done32);
+                                         finished, timing, done32);
             sweeps32 = sw32;
             tcol32 = ctx->host_ctl->tcol;
+            tcol64_base = tcol32;
+            if (status == HSVD_E_DEVICE) return status;
+            // A rank flag in an FP32 sweep may come from the FP32 Gram alone
+            // (it resolves S - |w| of a hyperbolic pair only to about sqrt(r)
+            // FP32 epsilons), and V32 is then no iterate to refine: the solve
+            // starts again from G in FP64, where a rank failure is final.
+            bool restart = status == HSVD_E_RANK;
             if (status == HSVD_OK) {
                 // back to FP64: X = J-orthogonalised V32, G1 = G X, V0 = X
-                HSVD_TRY(hipEventRecord(ev[2], st));
+                if (timing) HSVD_TRY(hipEventRecord(ev[2], st));
                 HSVD_TRY(launch_promote(st, w.V32, w.V, ldg, r));
                 s = reorthogonalise(ctx, w, n, r, p, ldg, ns_iters, ns_resid);
                 if (s != HSVD_OK) return s;
-                HSVD_TRY(hipEventRecord(ev[3], st));
-                HSVD_TRY(hipStreamSynchronize(st));
-                float ms = 0.f;
-                HSVD_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
-                kms[HSVD_K_REORTH] += ms;
+                if (timing) {
+                    HSVD_TRY(hipEventRecord(ev[3], st));
+                    HSVD_TRY(hipStreamSynchronize(st));
+                    float ms = 0.f;
+                    HSVD_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
+                    kms[HSVD_K_REORTH] += ms;
+                    ktimed[HSVD_K_REORTH] += 1;
+                }
                 klaunch[HSVD_K_REORTH] += 1;
-                ktimed[HSVD_K_REORTH] += 1;
-                HSVD_TRY(launch_colnorm_pos<double>(st, w.G, ldg, w.rho, w.d, r));
-                if (prm.sort) HSVD_TRY(launch_sort(st, w.d, w.rho, w.dtmp, w.rtmp, r, p));
+                // X not J-orthogonal to working accuracy (the iteration left its
+                // basin, stalled, or hit its cap): G X and V0 = X would carry
+                // that error into the result, so start again in FP64 as well
+                restart = !(ns_resid <= reorth_accept_bound(prm, n));
+                if (!restart) {
+                    HSVD_TRY(launch_colnorm_pos<double>(st, w.G, ldg, w.rho, w.d, r));
+                    if (prm.sort) HSVD_TRY(launch_sort(st, w.d, w.rho, w.dtmp, w.rtmp, r, p));
+                }
+            }
+            if (restart) {
+                // the same launches as a plain FP64 solve from here on (the
+                // stepper restarts with the step count), so the result is that
+                // solve's
+                restarted = 1;
+                gstep = 0;
+                tcol64_base = 0;
+                status = HSVD_OK;
+                s = start();
+                if (s != HSVD_OK) return s;
+                if (ctx->host_ctl->inval) status = HSVD_E_INVAL;
+                else if (ctx->host_ctl->rank) status = HSVD_E_RANK;
             }
         }
         if (status == HSVD_OK) {
@@ -791,7 +857,7 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             auto done64 = [](const SweepResult &sr) { return (sr.code & 2) == 0; };  // eq. (4.2)
             status = block_sweeps<double>(ctx, w, ba, w.G, pairs, steps_per_sweep, max_sweeps, prm.sort != 0, r, p,
                                           ldg, gstep, HSVD_K_BLOCK_GRAM, kms, klaunch, ktimed, sweeps, steps, last,
-                                          finished, done64);
+                                          finished, timing, done64);
             code = last.code;
             maxt_last = last.maxt;
             if (status == HSVD_OK && !finished) status = HSVD_E_NOCONV;
@@ -800,16 +866,17 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
     }
 
     HSVD_TRY(launch_finalize(st, w, n, r, p, ldg, sigma, U, ldu, V, ldv, lambda, perm));
-    HSVD_TRY(hipEventRecord(ev[1], st));
+    if (timing) HSVD_TRY(hipEventRecord(ev[1], st));
     HSVD_TRY(hipStreamSynchronize(st));
     if (info) {
         float ms = 0.f;
-        hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (timing) hipEventElapsedTime(&ms, ev[0], ev[1]);
         info->status = status;
         info->sweeps = sweeps;
         info->sweeps_fp32 = sweeps32;
         info->reorth_iters = ns_iters;
         info->reorth_resid = ns_resid;
+        info->fp64_restart = restarted;
         info->max_t_last = maxt_last;
         info->code = code;
         info->r = r;
@@ -835,11 +902,14 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
             info->kernel_bytes[HSVD_K_PAIR_STEP] = rot * 32.0 * rows * vmul + skp * 16.0 * rows;
             info->kernel_flops[HSVD_K_PAIR_STEP] = rot * (12.0 + 6.0 * (vmul - 1.0)) * rows + skp * 2.0 * rows;
         } else {
-            // per block pair and step: the Gram reads 2b columns and does a full
-            // (2b)^2 x rows product; the update must read and write only the
-            // columns of G (and of V) that a rotation touched, each the product
-            // of 2b columns with a column of W (2b x rows multiply-adds).  The
-            // FP32 phase of the mixed path always carries V.
+            // per block pair and step: the Gram reads 2b columns and issues the
+            // upper 10 of the 16 tiles of the (2b)^2 x rows product; the update
+            // must read and write only the columns of G (and of V) that a
+            // rotation touched, each the product of 2b columns with a column of
+            // W (2b x rows multiply-adds).  The inner launch's own traffic
+            // (partial Grams in, W out) belongs to splitting the Gram's rows,
+            // not to the method, and is not counted.  The FP32 phase of the
+            // mixed path always carries V.
             const double b2 = 2.0 * b;
             const double tc_all = (double)ctx->host_ctl->tcol;
             const double st64 = (double)klaunch[HSVD_K_BLOCK_GRAM], st32 = (double)klaunch[HSVD_K_BLOCK_GRAM32];
@@ -847,33 +917,33 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, int n, int p, co
                 const int kb = prec == 0 ? HSVD_K_BLOCK_GRAM : HSVD_K_BLOCK_GRAM32;
                 const double esz = prec == 0 ? 8.0 : 4.0;
                 const double visits = (prec == 0 ? st64 : st32) * pairs;
-                const double tcols = prec == 0 ? tc_all - (double)tcol32 : (double)tcol32;
+                const double tcols = prec == 0 ? tc_all - (double)tcol64_base : (double)tcol32;
                 const double vm = prec == 0 ? vmul : 2.0;
                 // with V carried by the block-oriented method, V's half of the
                 // update runs inside the inner launches and is counted there
                 const double vin = (vm > 1.0 && prm.inner_sweeps == 0) ? 1.0 : 0.0;
                 info->kernel_bytes[kb] = visits * esz * b2 * rows;
-                info->kernel_flops[kb] = visits * 2.0 * b2 * b2 * rows;
-                info->kernel_bytes[kb + 1] = visits * (double)(splits * esz + 2 * esz) * b2 * b2 +
-                                             vin * tcols * 2.0 * esz * rows;
+                info->kernel_flops[kb] = visits * 2.0 * (10.0 / 16.0) * b2 * b2 * rows;
+                info->kernel_bytes[kb + 1] = vin * tcols * 2.0 * esz * rows;
                 info->kernel_flops[kb + 1] = vin * tcols * 2.0 * b2 * rows;
                 info->kernel_bytes[kb + 2] = tcols * 2.0 * esz * rows * (vm - vin);
                 info->kernel_flops[kb + 2] = tcols * 2.0 * b2 * rows * (vm - vin);
             }
-            if (mixed) {
-                const double rr = (double)r;
-                info->kernel_flops[HSVD_K_REORTH] = (2.0 * ns_iters + 1.0 + 1.0) * 2.0 * rr * rr * rr;
+            if (mixed && klaunch[HSVD_K_REORTH] > 0) {
+                // X^T J X formed iters + 1 times (upper tiles only: a fraction
+                // (T + 1) / 2T of the product with T tiles per side), X T iters
+                // times, G X once; each product reads two r x r matrices and
+                // writes one
+                const double rr = (double)r, nt = (double)((r + 127) / 128);
+                const double full = 2.0 * rr * rr * rr;
+                info->kernel_flops[HSVD_K_REORTH] =
+                    (ns_iters + 1.0) * full * (nt + 1.0) / (2.0 * nt) + (ns_iters + 1.0) * full;
                 info->kernel_bytes[HSVD_K_REORTH] = (2.0 * ns_iters + 2.0) * 3.0 * 8.0 * rr * rr;
             }
         }
     }
     return status;
 }
-
-
-}  // extern "C"
-
-namespace {
 
 size_t take_bytes(size_t &o, size_t bytes)
 {
@@ -882,28 +952,52 @@ size_t take_bytes(size_t &o, size_t bytes)
     return at;
 }
 
+// Device buffer of the context for the partitioned solve (outside the solver's workspace).
+hsvd_status ensure_aux(hsvd_ctx *ctx, size_t bytes)
+{
+    if (ctx->aux_bytes >= bytes) return HSVD_OK;
+    if (ctx->aux) {
+        HSVD_TRY(hipStreamSynchronize(ctx->stream));
+        hipFree(ctx->aux);
+        ctx->aux = nullptr;
+        ctx->aux_bytes = 0;
+    }
+    if (hipMalloc(&ctx->aux, bytes) != hipSuccess) return HSVD_E_NOMEM;
+    ctx->aux_bytes = bytes;
+    return HSVD_OK;
+}
+
 }  // namespace
 
-extern "C" hsvd_status hsvd_solve_j(hsvd_ctx *ctx, const double *G, int lda, int n, const signed char *jsig,
-                                    const hsvd_params *prm_in, double *sigma, double *U, int ldu, double *V,
-                                    int ldv, double *lambda, int *perm, hsvd_info *info)
+extern "C" hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, const signed char *jsig, int n, int p,
+                                  const hsvd_params *prm_in, double *sigma, double *U, int ldu, double *V, int ldv,
+                                  double *lambda, int *perm, hsvd_info *info)
 {
     if (info) memset(info, 0, sizeof(*info));
-    if (!ctx || !G || !jsig || !sigma || n < 1 || lda < n) return HSVD_E_INVAL;
+    if (!ctx || !G || !sigma || n < 1 || p < 0 || p > n || lda < n) return HSVD_E_INVAL;
     if (U && ldu < n) return HSVD_E_INVAL;
     if (V && ldv < n) return HSVD_E_INVAL;
+    hsvd_params prm;
+    if (prm_in) prm = *prm_in;
+    else hsvd_default_params(&prm);
+    const SolveMode mode;
+    if (!jsig) return solve_canonical(ctx, G, lda, n, p, prm, sigma, U, ldu, V, ldv, lambda, perm, info, mode);
     HSVD_TRY(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     std::vector<signed char> hj(n);
     HSVD_TRY(hipMemcpyAsync(hj.data(), jsig, n, hipMemcpyDeviceToHost, st));
     HSVD_TRY(hipStreamSynchronize(st));
+    // stable partition: the +1 columns first, each class in input order
     std::vector<int> pi;
     pi.reserve(n);
     for (int c = 0; c < n; ++c) {
         if (hj[c] != 1 && hj[c] != -1) return HSVD_E_INVAL;
         if (hj[c] == 1) pi.push_back(c);
     }
-    const int p = (int)pi.size();
+    if ((int)pi.size() != p) return HSVD_E_INVAL;
+    bool canonical = true;
+    for (int c = 0; c < p; ++c) canonical = canonical && pi[c] == c;
+    if (canonical) return solve_canonical(ctx, G, lda, n, p, prm, sigma, U, ldu, V, ldv, lambda, perm, info, mode);
     for (int c = 0; c < n; ++c)
         if (hj[c] == -1) pi.push_back(c);
     // aux: pi, Gp, sigma_p, lambda_p, perm_p, U_p, V_p
@@ -911,31 +1005,22 @@ extern "C" hsvd_status hsvd_solve_j(hsvd_ctx *ctx, const double *G, int lda, int
     const size_t nn = (size_t)n * n;
     const size_t o_pi = take_bytes(o, sizeof(int) * n), o_Gp = take_bytes(o, sizeof(double) * nn);
     const size_t o_s = take_bytes(o, sizeof(double) * n), o_l = take_bytes(o, sizeof(double) * n);
-    const size_t o_pm = take_bytes(o, sizeof(int) * n), o_U = take_bytes(o, sizeof(double) * nn);
-    const size_t o_V = take_bytes(o, sizeof(double) * nn);
-    if (ctx->aux_bytes < o) {
-        if (ctx->aux) {
-            HSVD_TRY(hipStreamSynchronize(st));
-            hipFree(ctx->aux);
-            ctx->aux = nullptr;
-            ctx->aux_bytes = 0;
-        }
-        if (hipMalloc(&ctx->aux, o) != hipSuccess) return HSVD_E_NOMEM;
-        ctx->aux_bytes = o;
-    }
+    const size_t o_pm = take_bytes(o, sizeof(int) * n), o_U = take_bytes(o, U ? sizeof(double) * nn : 0);
+    const size_t o_V = take_bytes(o, V ? sizeof(double) * nn : 0);
+    hsvd_status s = ensure_aux(ctx, o);
+    if (s != HSVD_OK) return s;
     char *a = static_cast<char *>(ctx->aux);
     int *dpi = reinterpret_cast<int *>(a + o_pi);
     double *Gp = reinterpret_cast<double *>(a + o_Gp);
     double *sp = reinterpret_cast<double *>(a + o_s), *lp = reinterpret_cast<double *>(a + o_l);
     int *pmp = reinterpret_cast<int *>(a + o_pm);
-    double *Up = reinterpret_cast<double *>(a + o_U), *Vp = reinterpret_cast<double *>(a + o_V);
+    double *Up = U ? reinterpret_cast<double *>(a + o_U) : nullptr;
+    double *Vp = V ? reinterpret_cast<double *>(a + o_V) : nullptr;
     HSVD_TRY(hipMemcpyAsync(dpi, pi.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
     HSVD_TRY(launch_gather_cols(st, G, lda, dpi, Gp, n));
-    const hsvd_status s = hsvd_solve(ctx, Gp, n, n, p, prm_in, sp, U ? Up : nullptr, n, V ? Vp : nullptr, n,
-                                     lp, pmp, info);
+    s = solve_canonical(ctx, Gp, n, n, p, prm, sp, Up, n, Vp, n, lp, pmp, info, mode);
     if (s == HSVD_E_INVAL || s == HSVD_E_DEVICE || s == HSVD_E_NOMEM) return s;
-    HSVD_TRY(launch_scatter_outputs(st, dpi, n, sp, U ? Up : nullptr, V ? Vp : nullptr, lp, pmp, sigma, U, ldu,
-                                    V, ldv, lambda, perm));
+    HSVD_TRY(launch_scatter_outputs(st, dpi, n, sp, Up, Vp, lp, pmp, sigma, U, ldu, V, ldv, lambda, perm));
     HSVD_TRY(hipStreamSynchronize(st));
     return s;
 }
@@ -949,16 +1034,8 @@ extern "C" hsvd_status hsvd_autotune(hsvd_ctx *ctx, int n, int *best_algo, int *
     size_t o = 0;
     const size_t nn = (size_t)n * n;
     const size_t o_G = take_bytes(o, sizeof(double) * nn), o_s = take_bytes(o, sizeof(double) * n);
-    if (ctx->aux_bytes < o) {
-        if (ctx->aux) {
-            HSVD_TRY(hipStreamSynchronize(st));
-            hipFree(ctx->aux);
-            ctx->aux = nullptr;
-            ctx->aux_bytes = 0;
-        }
-        if (hipMalloc(&ctx->aux, o) != hipSuccess) return HSVD_E_NOMEM;
-        ctx->aux_bytes = o;
-    }
+    const hsvd_status sa = ensure_aux(ctx, o);
+    if (sa != HSVD_OK) return sa;
     double *G = reinterpret_cast<double *>(static_cast<char *>(ctx->aux) + o_G);
     double *sig = reinterpret_cast<double *>(static_cast<char *>(ctx->aux) + o_s);
     HSVD_TRY(launch_synth(st, G, n, 0x5EEDull + (unsigned long long)n));
@@ -980,8 +1057,8 @@ extern "C" hsvd_status hsvd_autotune(hsvd_ctx *ctx, int n, int *best_algo, int *
         hsvd_info info;
         double t = 0.0;
         for (int rep = 0; rep < 2; ++rep) {  // the first run also warms up
-            const hsvd_status s = hsvd_solve(ctx, G, n, n, n / 2, &prm, sig, nullptr, n, nullptr, n, nullptr,
-                                             nullptr, &info);
+            const hsvd_status s = hsvd_solve(ctx, G, n, nullptr, n, n / 2, &prm, sig, nullptr, n, nullptr, n,
+                                             nullptr, nullptr, &info);
             if (s != HSVD_OK && s != HSVD_E_NOCONV) {
                 ctx->tune[bucket] = saved;
                 return s;
@@ -1008,12 +1085,14 @@ extern "C" hsvd_status hsvd_autotune(hsvd_ctx *ctx, int n, int *best_algo, int *
 // single mixed solve, per problem.  FP32 block sweeps run until every problem
 // has left FP32 by its own switch rule (a problem out of FP32 is skipped by
 // the later FP32 launches); the Newton-Schulz iteration runs on the whole
-// group with strided batched GEMMs, each problem applying its corrections
-// until its own residual stops falling quadratically.  The FP64 sweeps then
-// start from (G1, V0 = X).
+// group with the batched FP64 MFMA products, each problem applying its
+// corrections until its own residual stops falling quadratically.  The FP64
+// sweeps then start from (G1, V0 = X), or from G for a problem that restarts
+// (rank flag in its FP32 phase, or a final residual above the accepted one).
 static hsvd_status batch_mixed_phase(hsvd_ctx *ctx, hipStream_t st, const BatchGroup &g, const BatchMixed &m,
                                      const BlockArgsT<double> &ba, int4 *S2, int pairs, int steps_per_sweep,
-                                     int max_sweeps, bool sort, long long &gstep, int *host_active, int &sweeps32)
+                                     int max_sweeps, bool sort, long long &gstep, int *host_active, int &sweeps32,
+                                     const double *Gin)
 {
     HSVD_TRY(launch_batch_mixed_init(st, g, m));
     BlockArgsT<float> fa;
@@ -1066,47 +1145,67 @@ static hsvd_status batch_mixed_phase(hsvd_ctx *ctx, hipStream_t st, const BatchG
         ++sweeps32;
         if (*host_active == 0) break;
     }
-    // V = V32 promoted; Newton-Schulz X <- X (3I - J X^T J X) / 2 per problem
+    // V = V32 promoted; Newton-Schulz X <- X (3I - J X^T J X) / 2 per problem,
+    // on the FP64 MFMA products with the problem in blockIdx.z
     HSVD_TRY(launch_batch_promote(st, g, m));
-    if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success) return HSVD_E_DEVICE;
-    BLAS_TRY(rocblas_set_stream(ctx->blas, st));
-    const double one = 1.0, zero = 0.0;
     const int r = g.r, ld = g.ldg;
-    const rocblas_stride mat = (rocblas_stride)g.ldg * g.r;
-    for (int it = 0; it < 6; ++it) {
-        HSVD_TRY(launch_batch_rowsign(st, g, m));  // T1 = J X
-        BLAS_TRY(rocblas_dgemm_strided_batched(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, r, r,
-                                               r, &one, g.V, ld, mat, m.T1, ld, mat, &zero, m.T2, ld, mat,
-                                               g.nprob));  // T2 = X^T J X
-        HSVD_TRY(launch_batch_ns_form(st, g, m));           // T2 = (3I - J X^T J X) / 2, residuals
-        HSVD_TRY(launch_batch_ns_decide(st, g, m, it));
+    const long long mat = (long long)g.ldg * g.r;
+    GemmArgs sy;  // T2 = X^T J X for the problems still iterating
+    sy.A = g.V;
+    sy.B = g.V;
+    sy.C = m.T2;
+    sy.M = sy.N = sy.K = r;
+    sy.lda = sy.ldb = sy.ldc = ld;
+    sy.sa = sy.sb = sy.sc = mat;
+    sy.pvec = g.p;
+    sy.flag = m.nsdone;
+    sy.want = 0;
+    GemmArgs xt = sy;  // T1 = X T2 where the correction applies
+    xt.B = m.T2;
+    xt.C = m.T1;
+    xt.pvec = nullptr;
+    xt.flag = m.apply;
+    xt.want = 1;
+    for (int it = 0; it <= 6; ++it) {
+        HSVD_TRY(launch_gemm(st, sy, g.nprob, true, true, true));
+        HSVD_TRY(launch_batch_ns_form(st, g, m));  // T2 = (3I - J X^T J X) / 2, residuals
+        HSVD_TRY(launch_batch_ns_decide(st, g, m, it, it == 6));
         HSVD_TRY(hipMemcpyAsync(host_active, g.active_count, sizeof(int), hipMemcpyDeviceToHost, st));
         HSVD_TRY(hipStreamSynchronize(st));
         if (*host_active == 0) break;
-        BLAS_TRY(rocblas_dgemm_strided_batched(ctx->blas, rocblas_operation_none, rocblas_operation_none, r, r, r,
-                                               &one, g.V, ld, mat, m.T2, ld, mat, &zero, m.T1, ld, mat,
-                                               g.nprob));  // T1 = X T2
+        HSVD_TRY(launch_gemm(st, xt, g.nprob, false, false, false));
         HSVD_TRY(launch_batch_copy_if(st, g, m.T1, g.V, m.apply, false));
     }
-    // G1 = G X for every running problem
-    BLAS_TRY(rocblas_dgemm_strided_batched(ctx->blas, rocblas_operation_none, rocblas_operation_none, r, r, r, &one,
-                                           g.G, ld, mat, g.V, ld, mat, &zero, m.T1, ld, mat, g.nprob));
-    HSVD_TRY(launch_batch_copy_if(st, g, m.T1, g.G, g.done, true));
+    // problems whose X is not J-orthogonal to working accuracy (or whose FP32
+    // phase saw a rank flag) restart from G in FP64; the others go on from
+    // G1 = G X (apply marks them)
+    HSVD_TRY(launch_batch_ns_accept(st, g, m));
+    GemmArgs gx = sy;
+    gx.A = g.G;
+    gx.B = g.V;
+    gx.C = m.T1;
+    gx.pvec = nullptr;
+    gx.flag = m.apply;
+    gx.want = 1;
+    HSVD_TRY(launch_gemm(st, gx, g.nprob, false, false, false));
+    HSVD_TRY(launch_batch_copy_if(st, g, m.T1, g.G, m.apply, false));
+    BatchGroup gr = g;
+    gr.only = m.restart;
+    HSVD_TRY(launch_batch_setup(st, gr, Gin, true));
     // the kept diagonal of G1 and the sort, as after a sweep
     HSVD_TRY(launch_batch_colnorm(st, g, false));
     if (sort) HSVD_TRY(launch_batch_sort(st, g));
     return HSVD_OK;
 }
 
-extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n, const int *p,
-                                          const long long *off, const long long *voff, const double *G,
+extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n_in, const int *p_in,
+                                          const long long *off_in, const long long *voff_in, const double *G,
                                           const hsvd_params *prm_in, double *sigma, double *U, double *V,
-                                          double *lambda, int *status_out, int *sweeps_out, hsvd_info *info)
+                                          double *lambda, hsvd_info *info)
 {
-    if (info) memset(info, 0, sizeof(*info));
     if (!ctx || batch < 0) return HSVD_E_INVAL;
     if (batch == 0) return HSVD_OK;
-    if (!n || !p || !off || !voff || !G || !sigma) return HSVD_E_INVAL;
+    if (!n_in || !p_in || !off_in || !voff_in || !G || !sigma) return HSVD_E_INVAL;
     hsvd_params prm;
     if (prm_in) prm = *prm_in;
     else hsvd_default_params(&prm);
@@ -1119,12 +1218,21 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
     if (V && !want_v) return HSVD_E_INVAL;
     // the mixed path carries V through its FP32 phase even when it is not returned
     const bool acc_v = want_v || mixed;
+    HSVD_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    // the per-problem metadata, device or host memory, to the host once: it
+    // decides the groups and their launch shapes
+    std::vector<int> n(batch), p(batch);
+    std::vector<long long> off(batch), voff(batch);
+    HSVD_TRY(hipMemcpyAsync(n.data(), n_in, sizeof(int) * batch, hipMemcpyDefault, st));
+    HSVD_TRY(hipMemcpyAsync(p.data(), p_in, sizeof(int) * batch, hipMemcpyDefault, st));
+    HSVD_TRY(hipMemcpyAsync(off.data(), off_in, sizeof(long long) * batch, hipMemcpyDefault, st));
+    HSVD_TRY(hipMemcpyAsync(voff.data(), voff_in, sizeof(long long) * batch, hipMemcpyDefault, st));
+    HSVD_TRY(hipStreamSynchronize(st));
     for (int k = 0; k < batch; ++k)
         if (n[k] < 1 || n[k] > 1024 || p[k] < 0 || p[k] > n[k] || off[k] < 0 || voff[k] < 0) return HSVD_E_INVAL;
     const int max_sweeps = prm.max_sweeps > 0 ? prm.max_sweeps : 100;
     const int b = block_width();
-    HSVD_TRY(hipSetDevice(ctx->device));
-    hipStream_t st = ctx->stream;
     hsvd_status s = ensure_events(ctx, 4 + 4 * 1024 / b);
     if (s != HSVD_OK) return s;
     hipEvent_t *ev = ctx->events.data();
@@ -1133,13 +1241,9 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
     std::vector<std::vector<int>> groups(1024 / (2 * b) + 1);
     for (int k = 0; k < batch; ++k) groups[(n[k] + 2 * b - 1) / (2 * b)].push_back(k);
 
-    double kms[HSVD_NKERNELS] = {0};
-    long long klaunch[HSVD_NKERNELS] = {0};
-    long long ktimed[HSVD_NKERNELS] = {0};
-    double kbytes[HSVD_NKERNELS] = {0}, kflops[HSVD_NKERNELS] = {0};
-    long long tot_rot = 0, tot_skip = 0, tot_act = 0, tot_steps = 0;
-    int max_sw = 0, max_sw32 = 0;
-    std::vector<int> all_status(batch, HSVD_OK), all_sweeps(batch, 0);
+    // per-problem results, filled group by group
+    std::vector<hsvd_info> pinfo(batch);
+    memset(pinfo.data(), 0, sizeof(hsvd_info) * batch);
     HSVD_TRY(hipEventRecord(ev[0], st));
     for (size_t gi = 1; gi < groups.size(); ++gi) {
         const std::vector<int> &ids = groups[gi];
@@ -1181,6 +1285,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         const size_t o_t32 = take_bytes(o, sizeof(double) * mx_k), o_h32 = take_bytes(o, sizeof(double) * mx_k);
         const size_t o_ap = take_bytes(o, sizeof(int) * mx_k), o_nd = take_bytes(o, sizeof(int) * mx_k);
         const size_t o_np = take_bytes(o, sizeof(double) * mx_k);
+        const size_t o_ni = take_bytes(o, sizeof(int) * mx_k), o_rs = take_bytes(o, sizeof(int) * mx_k);
         s = ensure_ws(ctx, o);
         if (s != HSVD_OK) return s;
         char *base = static_cast<char *>(ctx->ws);
@@ -1289,11 +1394,28 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
             m.apply = reinterpret_cast<int *>(base + o_ap);
             m.nsdone = reinterpret_cast<int *>(base + o_nd);
             m.nsprev = reinterpret_cast<double *>(base + o_np);
+            m.nsiters = reinterpret_cast<int *>(base + o_ni);
+            m.restart = reinterpret_cast<int *>(base + o_rs);
+            m.accept = prm.reorth_accept;
             int sw32 = 0;
             s = batch_mixed_phase(ctx, st, g, m, ba, S2, pairs, steps_per_sweep, max_sweeps, prm.sort != 0, gstep,
-                                  host_active, sw32);
+                                  host_active, sw32, G);
             if (s != HSVD_OK) return s;
-            max_sw32 = max_sw32 > sw32 ? max_sw32 : sw32;
+            // per-problem FP32 sweeps, corrections, final residuals, restarts
+            std::vector<int> h32(K), hni(K), hrs(K);
+            std::vector<double> hres(K);
+            HSVD_TRY(hipMemcpyAsync(h32.data(), m.sweeps32, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+            HSVD_TRY(hipMemcpyAsync(hni.data(), m.nsiters, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+            HSVD_TRY(hipMemcpyAsync(hrs.data(), m.restart, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+            HSVD_TRY(hipMemcpyAsync(hres.data(), m.nsprev, sizeof(double) * K, hipMemcpyDeviceToHost, st));
+            HSVD_TRY(hipStreamSynchronize(st));
+            for (int z = 0; z < K; ++z) {
+                hsvd_info &pi = pinfo[ids[z]];
+                pi.sweeps_fp32 = h32[z];
+                pi.reorth_iters = hni[z];
+                pi.fp64_restart = hrs[z];
+                pi.reorth_resid = hres[z] <= 1.0 ? hres[z] : 0.0;
+            }
         }
         // one sweep: the outer steps, the kept diagonal, the sort, the stop rule
         auto enqueue_sweep = [&](hipStream_t q, bool timed) -> hipError_t {
@@ -1348,23 +1470,10 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
                 HSVD_TRY(hipGraphLaunch(exec, q));
                 gstep += steps_per_sweep;
             } else {
-                HSVD_TRY(enqueue_sweep(q, true));
+                HSVD_TRY(enqueue_sweep(q, false));
             }
-            for (int qk = 0; qk < 3; ++qk) klaunch[HSVD_K_BLOCK_GRAM + qk] += steps_per_sweep;
-            tot_steps += steps_per_sweep;
             HSVD_TRY(hipStreamSynchronize(q));
             const int active = *host_active;
-            if (!prm.graph) {
-                for (int k = 0; k < steps_per_sweep; ++k) {
-                    hipEvent_t *e = ev + 4 + 4 * k;
-                    for (int qk = 0; qk < 3; ++qk) {
-                        float ms = 0.f;
-                        HSVD_TRY(hipEventElapsedTime(&ms, e[qk], e[qk + 1]));
-                        kms[HSVD_K_BLOCK_GRAM + qk] += ms;
-                    }
-                }
-                for (int qk = 0; qk < 3; ++qk) ktimed[HSVD_K_BLOCK_GRAM + qk] += steps_per_sweep;
-            }
             ++gsweeps;
             if (active == 0) break;
         }
@@ -1381,56 +1490,34 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
         HSVD_TRY(hipMemcpyAsync(hsw.data(), g.sweeps, sizeof(int) * K, hipMemcpyDeviceToHost, st));
         HSVD_TRY(hipMemcpyAsync(hctl.data(), g.ctl, sizeof(Ctl) * K, hipMemcpyDeviceToHost, st));
         HSVD_TRY(hipStreamSynchronize(st));
-        long long act = 0, tcol = 0;
         for (int z = 0; z < K; ++z) {
-            all_status[ids[z]] = hs[z];
-            all_sweeps[ids[z]] = hsw[z];
-            if (hsw[z] > max_sw) max_sw = hsw[z];
-            tot_rot += (long long)hctl[z].rot;
-            tot_skip += (long long)hctl[z].skip;
-            act += (long long)hctl[z].act;
-            tcol += (long long)hctl[z].tcol;
+            hsvd_info &pi = pinfo[ids[z]];
+            pi.status = hs[z];
+            pi.sweeps = hsw[z];
+            pi.code = hctl[z].code;
+            pi.r = r;
+            pi.block = b;
+            pi.ldg = ldg;
+            pi.max_t_last = hctl[z].maxt;
+            pi.rotations = (long long)hctl[z].rot;
+            pi.skips = (long long)hctl[z].skip;
+            pi.steps = (long long)hsw[z] * steps_per_sweep;
+            pi.active_pairs = (long long)hctl[z].act;
         }
-        tot_act += act;
-        // algorithmic work of the group (see hsvd_solve): Gram of every pair
-        // step of every problem still running, update of the active ones
-        long long visits = 0;
-        for (int z = 0; z < K; ++z) visits += (long long)hsw[z] * steps_per_sweep * pairs;
-        const double b2 = 2.0 * b, rows = (double)ldg, vmul = want_v ? 2.0 : 1.0;
-        kbytes[HSVD_K_BLOCK_GRAM] += (double)visits * 8.0 * b2 * rows;
-        kflops[HSVD_K_BLOCK_GRAM] += (double)visits * 2.0 * b2 * b2 * rows;
-        kbytes[HSVD_K_BLOCK_INNER] += (double)visits * 3.0 * 8.0 * b2 * b2;
-        kbytes[HSVD_K_BLOCK_UPDATE] += (double)tcol * 16.0 * rows * vmul;
-        kflops[HSVD_K_BLOCK_UPDATE] += (double)tcol * 2.0 * b2 * rows * vmul;
         (void)gsweeps;
     }
     HSVD_TRY(hipEventRecord(ev[1], st));
     HSVD_TRY(hipStreamSynchronize(st));
+    float ms = 0.f;
+    HSVD_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
     hsvd_status result = HSVD_OK;
     for (int k = 0; k < batch; ++k) {
-        if (status_out) status_out[k] = all_status[k];
-        if (sweeps_out) sweeps_out[k] = all_sweeps[k];
-        if (result == HSVD_OK && all_status[k] != HSVD_OK) result = (hsvd_status)all_status[k];
+        pinfo[k].ms_total = ms;
+        if (result == HSVD_OK && pinfo[k].status != HSVD_OK) result = (hsvd_status)pinfo[k].status;
     }
     if (info) {
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, ev[0], ev[1]);
-        info->status = result;
-        info->sweeps = max_sw;
-        info->sweeps_fp32 = max_sw32;
-        info->block = b;
-        info->rotations = tot_rot;
-        info->skips = tot_skip;
-        info->steps = tot_steps;
-        info->active_pairs = tot_act;
-        info->ms_total = ms;
-        for (int q = 0; q < HSVD_NKERNELS; ++q) {
-            info->kernel_ms[q] = kms[q];
-            info->kernel_launches[q] = klaunch[q];
-            info->kernel_timed[q] = ktimed[q];
-            info->kernel_bytes[q] = kbytes[q];
-            info->kernel_flops[q] = kflops[q];
-        }
+        HSVD_TRY(hipMemcpyAsync(info, pinfo.data(), sizeof(hsvd_info) * batch, hipMemcpyDefault, st));
+        HSVD_TRY(hipStreamSynchronize(st));
     }
     return result;
 }

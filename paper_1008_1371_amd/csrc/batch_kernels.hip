@@ -16,6 +16,7 @@ __global__ __launch_bounds__(256) void batch_setup_kernel(BatchGroup g, const do
                                                           int want_v)
 {
     const int c = blockIdx.x, z = blockIdx.y;
+    if (g.only && !g.only[z]) return;
     const int n = g.n[z];
     const size_t mat = (size_t)g.ldg * g.r;
     double *gc = g.G + z * mat + (size_t)c * g.ldg;
@@ -39,6 +40,7 @@ __global__ __launch_bounds__(256) void batch_colnorm_kernel(BatchGroup g, int in
     __shared__ double sh[4];
     const int q = blockIdx.x, z = blockIdx.y;
     if (!init && g.done[z]) return;
+    if (init && g.only && !g.only[z]) return;
     const size_t mat = (size_t)g.ldg * g.r;
     int *rho = g.rho + (size_t)z * g.r;
     const int c = init ? q : rho[q];
@@ -109,6 +111,7 @@ __global__ void batch_init_decide_kernel(BatchGroup g)
 {
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
     if (z >= g.nprob) return;
+    if (g.only && !g.only[z]) return;
     const Ctl *ctl = g.ctl + z;
     g.sweeps[z] = 0;
     if (ctl->inval) {
@@ -208,11 +211,12 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(BatchGroup g, doubl
     }
 }
 
-__global__ void batch_zero_ctl_kernel(Ctl *ctl, int nprob, int *active_count)
+__global__ void batch_zero_ctl_kernel(Ctl *ctl, int nprob, int *active_count, const int *only)
 {
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
     if (z == 0) *active_count = 0;
     if (z >= nprob) return;
+    if (only && !only[z]) return;
     ctl[z].code = 0;
     ctl[z].rank = 0;
     ctl[z].inval = 0;
@@ -244,6 +248,8 @@ __global__ __launch_bounds__(256) void batch_mixed_init_kernel(BatchGroup g, Bat
         m.nsdone[z] = g.done[z];
         m.apply[z] = 0;
         m.nsprev[z] = 2.0;
+        m.nsiters[z] = 0;
+        m.restart[z] = 0;
         g.ctl[z].nsres = 0.0;
         // the FP32 Gram resolves cosines down to about sqrt(r) FP32 epsilons
         const double t32 = fmax(g.tol[z], sqrt((double)g.r) * 0x1p-23);
@@ -285,7 +291,10 @@ __global__ __launch_bounds__(256) void batch_colnorm32_kernel(BatchGroup g, Batc
 // stagnates below 0.1, when FP32 converged, when the fraction f of the
 // sweep's pair visits that rotated is below 1/100, or f <= 1/3 while falling
 // by less than a quarter per sweep (the rule of a single mixed solve), or at
-// max_sweeps.  A rank failure ends the problem.  grid nprob, 64 threads
+// max_sweeps.  A rank flag ends the FP32 phase and marks the problem for a
+// restart from G in FP64 (the FP32 Gram resolves S - |w| of a hyperbolic
+// pair only to about sqrt(r) FP32 epsilons; a rank failure is final only in
+// FP64).  grid nprob, 64 threads
 __global__ __launch_bounds__(64) void batch_decide32_kernel(BatchGroup g, BatchMixed m)
 {
     const int z = blockIdx.x;
@@ -321,10 +330,10 @@ __global__ __launch_bounds__(64) void batch_decide32_kernel(BatchGroup g, BatchM
         m.sweeps32[z] = sw;
         const double frac = rot + skp > 0 ? (double)rot / (double)(rot + skp) : 0.0;
         if (ctl->rank) {
-            g.status[z] = HSVD_E_RANK;
-            g.done[z] = 1;
+            ctl->rank = 0;
             m.done32[z] = 1;
             m.nsdone[z] = 1;
+            m.restart[z] = 1;
         } else {
             const double pm = m.prev_maxt[z], pf = m.prev_frac[z];
             const bool stop = mx <= 3e-4 || (code & 2) == 0 || (mx < 0.1 && mx > 0.25 * pm) || frac < 0.01 ||
@@ -346,19 +355,6 @@ __global__ __launch_bounds__(256) void batch_promote_kernel(BatchGroup g, BatchM
     const float *src = m.V32 + z * mat + (size_t)c * g.ldg;
     double *dst = g.V + z * mat + (size_t)c * g.ldg;
     for (int row = threadIdx.x; row < g.ldg; row += 256) dst[row] = (double)src[row];
-}
-
-// T1 = J X (X = V): row `row` of problem z negated iff row >= p[z] (the
-// bordering columns carry sign -1).  grid (r, nprob)
-__global__ __launch_bounds__(256) void batch_rowsign_kernel(BatchGroup g, BatchMixed m)
-{
-    const int c = blockIdx.x, z = blockIdx.y;
-    if (m.nsdone[z]) return;
-    const int p = g.p[z];
-    const size_t mat = (size_t)g.ldg * g.r;
-    const double *x = g.V + z * mat + (size_t)c * g.ldg;
-    double *t = m.T1 + z * mat + (size_t)c * g.ldg;
-    for (int row = threadIdx.x; row < g.ldg; row += 256) t[row] = row < p ? x[row] : -x[row];
 }
 
 // T2 holds X^T J X of problem z.  Y = J T2; T2 <- (3I - Y) / 2; the largest
@@ -395,7 +391,7 @@ __global__ __launch_bounds__(256) void batch_ns_form_kernel(BatchGroup g, BatchM
 // J-orthogonal to working accuracy (residual at the rounding floor of its n
 // real columns, or no longer falling quadratically); counts the problems it
 // applies to.  grid ceil(nprob / 256)
-__global__ void batch_ns_decide_kernel(BatchGroup g, BatchMixed m, int iter)
+__global__ void batch_ns_decide_kernel(BatchGroup g, BatchMixed m, int iter, int last)
 {
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
     if (z >= g.nprob) return;
@@ -406,15 +402,34 @@ __global__ void batch_ns_decide_kernel(BatchGroup g, BatchMixed m, int iter)
     const double resid = g.ctl[z].nsres;
     g.ctl[z].nsres = 0.0;
     const double floor_ = 16.0 * g.n[z] * 0x1p-53;
-    const bool stop = !(resid < 1.0) || resid <= floor_ || (iter > 0 && resid > 0.25 * m.nsprev[z]);
-    m.nsprev[z] = resid;
+    const bool stop =
+        last || !(resid < 1.0) || resid <= floor_ || (iter > 0 && resid > 0.25 * m.nsprev[z]);
+    m.nsprev[z] = resid;  // the residual of the current X: the final one once stopped
     if (stop) {
         m.nsdone[z] = 1;
         m.apply[z] = 0;
     } else {
         m.apply[z] = 1;
+        m.nsiters[z] += 1;
         atomicAdd(g.active_count, 1);
     }
+}
+
+// After the J-re-orthogonalisation: a problem whose final residual is above
+// the accepted bound (m.accept, or 16384 n u) restarts from G in FP64, like
+// one flagged rank deficient in its FP32 phase; apply[z] marks the problems
+// that go on from G1 = G X.  grid ceil(nprob / 256)
+__global__ void batch_ns_accept_kernel(BatchGroup g, BatchMixed m)
+{
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= g.nprob) return;
+    if (g.done[z]) {
+        m.apply[z] = 0;
+        return;
+    }
+    const double bound = m.accept > 0.0 ? m.accept : 16384.0 * g.n[z] * 0x1p-53;
+    if (!m.restart[z] && !(m.nsprev[z] <= bound)) m.restart[z] = 1;
+    m.apply[z] = m.restart[z] ? 0 : 1;
 }
 
 // dst_z <- src_z where flag[z] != 0 (invert: == 0).  grid (r, nprob)
@@ -456,24 +471,24 @@ hipError_t launch_batch_promote(hipStream_t st, const BatchGroup &g, const Batch
     return hipGetLastError();
 }
 
-hipError_t launch_batch_rowsign(hipStream_t st, const BatchGroup &g, const BatchMixed &m)
-{
-    batch_rowsign_kernel<<<dim3(g.r, g.nprob), 256, 0, st>>>(g, m);
-    return hipGetLastError();
-}
-
 hipError_t launch_batch_ns_form(hipStream_t st, const BatchGroup &g, const BatchMixed &m)
 {
     batch_ns_form_kernel<<<dim3(g.r, g.nprob), 256, 0, st>>>(g, m);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_ns_decide(hipStream_t st, const BatchGroup &g, const BatchMixed &m, int iter)
+hipError_t launch_batch_ns_decide(hipStream_t st, const BatchGroup &g, const BatchMixed &m, int iter, bool last)
 {
     batch_zero_count_kernel<<<1, 1, 0, st>>>(g.active_count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    batch_ns_decide_kernel<<<(g.nprob + 255) / 256, 256, 0, st>>>(g, m, iter);
+    batch_ns_decide_kernel<<<(g.nprob + 255) / 256, 256, 0, st>>>(g, m, iter, last ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_ns_accept(hipStream_t st, const BatchGroup &g, const BatchMixed &m)
+{
+    batch_ns_accept_kernel<<<(g.nprob + 255) / 256, 256, 0, st>>>(g, m);
     return hipGetLastError();
 }
 
@@ -486,7 +501,7 @@ hipError_t launch_batch_copy_if(hipStream_t st, const BatchGroup &g, const doubl
 
 hipError_t launch_batch_setup(hipStream_t st, const BatchGroup &g, const double *G, bool want_v)
 {
-    batch_zero_ctl_kernel<<<(g.nprob + 255) / 256, 256, 0, st>>>(g.ctl, g.nprob, g.active_count);
+    batch_zero_ctl_kernel<<<(g.nprob + 255) / 256, 256, 0, st>>>(g.ctl, g.nprob, g.active_count, g.only);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     batch_setup_kernel<<<dim3(g.r, g.nprob), 256, 0, st>>>(g, G, want_v ? 1 : 0);

@@ -410,6 +410,9 @@ struct BatchGroup {
     unsigned int *nrot, *nskip, *nact, *ntc;
     double *maxt;
     Ctl *ctl;
+    // set-up of a subset (the FP64 restart of mixed solves): the set-up
+    // launches touch only the problems with only[z] != 0
+    const int *only = nullptr;
 };
 hipError_t launch_batch_setup(hipStream_t st, const BatchGroup &g, const double *G, bool want_v);
 hipError_t launch_batch_colnorm(hipStream_t st, const BatchGroup &g, bool init);
@@ -428,17 +431,21 @@ struct BatchMixed {
     double *prev_maxt, *prev_frac;
     double *tol32, *tth32;
     double *T1, *T2;       // per problem ldg * r (FP64)
-    int *apply;            // the Newton-Schulz correction of this iteration applies
+    int *apply;            // the Newton-Schulz correction of this iteration applies; after it, G1 = G X applies
     int *nsdone;
-    double *nsprev;
+    double *nsprev;        // latest residual max |J X^T J X - I| (the final one once nsdone)
+    int *nsiters;          // corrections applied
+    int *restart;          // the problem starts again from G in FP64
+    double accept = 0.0;   // accepted final residual (<= 0: 16384 n u)
 };
 hipError_t launch_batch_mixed_init(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
 hipError_t launch_batch_colnorm32(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
 hipError_t launch_batch_decide32(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
 hipError_t launch_batch_promote(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
-hipError_t launch_batch_rowsign(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
 hipError_t launch_batch_ns_form(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
-hipError_t launch_batch_ns_decide(hipStream_t st, const BatchGroup &g, const BatchMixed &m, int iter);
+// last: the iteration cap, every problem stops after this residual
+hipError_t launch_batch_ns_decide(hipStream_t st, const BatchGroup &g, const BatchMixed &m, int iter, bool last);
+hipError_t launch_batch_ns_accept(hipStream_t st, const BatchGroup &g, const BatchMixed &m);
 // dst_z <- src_z (ldg x r) for the problems with flag[z] != 0 (invert: == 0)
 hipError_t launch_batch_copy_if(hipStream_t st, const BatchGroup &g, const double *src, double *dst,
                                 const int *flag, bool invert);
@@ -446,10 +453,30 @@ hipError_t launch_batch_copy_if(hipStream_t st, const BatchGroup &g, const doubl
 // mixed path helpers
 hipError_t launch_to_fp32(hipStream_t st, const double *G, float *G32, float *V32, int ldg, int r);
 hipError_t launch_promote(hipStream_t st, const float *X32, double *X, int ldg, int r);
-hipError_t launch_rowsign(hipStream_t st, const double *X, double *Z, int p, int ldg, int r);
 hipError_t launch_ns_form(hipStream_t st, double *B, int p, int ldg, int r, Ctl *ctl);
 hipError_t launch_copy(hipStream_t st, const double *src, double *dst, int ldg, int r);
 hipError_t launch_synth(hipStream_t st, double *G, int n, unsigned long long seed);
+// FP64 products of the J-re-orthogonalisation (gemm_kernels.hip):
+// C = op(A) S B, column-major, C M x N, K the inner dimension; op(A) = A
+// (A M x K) or A^T (A K x M); S = diag(+1 x p, -1 x (K - p)) on the rows of B
+// when signed.  The symmetric form (op(A) = A^T, M = N) forms the upper
+// tiles only and writes each to both triangles.  M and N multiples of 16, K
+// of 16, leading dimensions and strides even.  Batched (nprob > 1): problem
+// z = blockIdx.z at offsets z * (sa, sb, sc), p = pvec[z] when pvec is set,
+// and with flag set only the problems with (flag[z] != 0) == want run.
+struct GemmArgs {
+    const double *A = nullptr, *B = nullptr;
+    double *C = nullptr;
+    int M = 0, N = 0, K = 0;
+    int lda = 0, ldb = 0, ldc = 0;
+    long long sa = 0, sb = 0, sc = 0;
+    int p = 0;
+    const int *pvec = nullptr;
+    const int *flag = nullptr;
+    int want = 1;
+};
+hipError_t launch_gemm(hipStream_t st, const GemmArgs &g, int nprob, bool trans_a, bool signed_b, bool symmetric);
+
 hipError_t launch_gather_cols(hipStream_t st, const double *G, int lda, const int *pi, double *Gp, int n);
 hipError_t launch_scatter_outputs(hipStream_t st, const int *pi, int n, const double *sp, const double *Up,
                                   const double *Vp, const double *lp, const int *permp, double *sigma, double *U,

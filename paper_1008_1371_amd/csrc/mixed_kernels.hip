@@ -7,8 +7,8 @@
 // converges quadratically from X = V32 (promoted) while ||I - Y|| < 1; with X
 // J-orthogonal to FP64 accuracy the FP64 refinement sweeps start from
 // G1 = G X, V0 = X, so the final V = X V_refine is J-orthogonal in FP64.
-// The two products per iteration and G X are plain GEMMs (rocBLAS); these
-// kernels form J X, (3I - J B) / 2 and the residual.
+// The two products per iteration and G X run on the FP64 MFMA kernels of
+// gemm_kernels.hip; these kernels form (3I - J B) / 2 and the residual.
 #include "internal.h"
 
 namespace hsvd {
@@ -28,17 +28,6 @@ __global__ __launch_bounds__(256) void promote_kernel(const float *__restrict__ 
 {
     const int c = blockIdx.x;
     for (int row = threadIdx.x; row < ldg; row += 256) X[(size_t)c * ldg + row] = (double)X32[(size_t)c * ldg + row];
-}
-
-// Z = J X: row `row` scaled by the sign of physical column `row` (+1 iff row < p).
-__global__ __launch_bounds__(256) void rowsign_kernel(const double *__restrict__ X, double *__restrict__ Z,
-                                                      int p, int ldg, int r)
-{
-    const int c = blockIdx.x;
-    for (int row = threadIdx.x; row < ldg; row += 256) {
-        const double x = X[(size_t)c * ldg + row];
-        Z[(size_t)c * ldg + row] = (row < p || row >= r) ? x : -x;
-    }
 }
 
 // B holds X^T J X (r x r).  Y = J B; B <- (3I - Y) / 2; the largest |Y - I|
@@ -158,12 +147,6 @@ hipError_t launch_to_fp32(hipStream_t st, const double *G, float *G32, float *V3
 hipError_t launch_promote(hipStream_t st, const float *X32, double *X, int ldg, int r)
 {
     promote_kernel<<<r, 256, 0, st>>>(X32, X, ldg, r);
-    return hipGetLastError();
-}
-
-hipError_t launch_rowsign(hipStream_t st, const double *X, double *Z, int p, int ldg, int r)
-{
-    rowsign_kernel<<<r, 256, 0, st>>>(X, Z, p, ldg, r);
     return hipGetLastError();
 }
 

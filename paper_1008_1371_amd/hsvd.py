@@ -32,7 +32,7 @@ class hsvd_params(ctypes.Structure):
                 ("block", ctypes.c_int), ("sort", ctypes.c_int), ("want_v", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("tol", ctypes.c_double),
                 ("t_thresh", ctypes.c_double), ("graph", ctypes.c_int),
-                ("inner_sweeps", ctypes.c_int)]
+                ("inner_sweeps", ctypes.c_int), ("reorth_accept", ctypes.c_double)]
 
 
 NKERNELS = 8
@@ -40,7 +40,7 @@ NKERNELS = 8
  K_BLOCK_UPDATE32, K_REORTH) = range(NKERNELS)
 KERNEL_NAMES = ["pair_step_kernel", "block_gram_kernel<double>", "block_inner_kernel<double>",
                 "block_update_kernel<double>", "block_gram_kernel<float>",
-                "block_inner_kernel<float>", "block_update_kernel<float>", "reorth (rocBLAS dgemm)"]
+                "block_inner_kernel<float>", "block_update_kernel<float>", "gemm_f64_kernel (reorth)"]
 
 
 class hsvd_info(ctypes.Structure):
@@ -48,6 +48,7 @@ class hsvd_info(ctypes.Structure):
                 ("r", ctypes.c_int), ("block", ctypes.c_int), ("ldg", ctypes.c_int),
                 ("sweeps_fp32", ctypes.c_int), ("reorth_iters", ctypes.c_int),
                 ("max_t_last", ctypes.c_double), ("reorth_resid", ctypes.c_double),
+                ("fp64_restart", ctypes.c_int), ("pad_", ctypes.c_int),
                 ("rotations", ctypes.c_longlong), ("skips", ctypes.c_longlong),
                 ("steps", ctypes.c_longlong), ("active_pairs", ctypes.c_longlong),
                 ("ms_total", ctypes.c_double),
@@ -89,21 +90,19 @@ def lib():
     L.hsvd_destroy.argtypes = [vp]
     L.hsvd_default_params.argtypes = [ctypes.POINTER(hsvd_params)]
     L.hsvd_default_params.restype = None
-    L.hsvd_solve.argtypes = [vp, vp, ip, ip, ip, ctypes.POINTER(hsvd_params), vp, vp, ip, vp, ip,
+    L.hsvd_solve.argtypes = [vp, vp, ip, vp, ip, ip, ctypes.POINTER(hsvd_params), vp, vp, ip, vp, ip,
                              vp, vp, ctypes.POINTER(hsvd_info)]
     L.hsvd_pair_params.argtypes = [vp, ctypes.c_longlong, vp, vp, vp, vp, dp, dp, vp, vp, vp, vp,
                                    vp]
     L.hsvd_block_pair_params.argtypes = L.hsvd_pair_params.argtypes
     L.hsvd_autotune.argtypes = [vp, ip, ctypes.POINTER(ip), ctypes.POINTER(ip)]
-    L.hsvd_solve_j.argtypes = [vp, vp, ip, ip, vp, ctypes.POINTER(hsvd_params), vp, vp, ip, vp, ip,
-                               vp, vp, ctypes.POINTER(hsvd_info)]
     L.hsvd_pivot_trace.argtypes = [vp, ip, ip, ip, vp]
     L.hsvd_sort_diag.argtypes = [vp, ip, ip, vp, vp]
     L.hsvd_block_trace.argtypes = [vp, ip, ip, ip, ip, vp]
     L.hsvd_solve_batched.argtypes = [vp, ip, vp, vp, vp, vp, vp, ctypes.POINTER(hsvd_params), vp, vp,
-                                     vp, vp, vp, vp, ctypes.POINTER(hsvd_info)]
+                                     vp, vp, vp]
     L.hsvd_version.restype = ctypes.c_char_p
-    for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_solve_j", "hsvd_autotune",
+    for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_autotune",
                  "hsvd_pair_params",
                  "hsvd_block_pair_params",
                  "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_block_trace", "hsvd_solve_batched"):
@@ -189,17 +188,25 @@ def hsvd_default_params(**overrides) -> hsvd_params:
     return prm
 
 
-def hsvd_solve(ctx: Context, G, p: int, params: hsvd_params | None = None, *, want_u=True,
-               want_v=None, want_lambda=True, want_perm=True, out=None, check=True):
-    """Solves G = U Sigma V^T, V^T J V = J with J = diag(I_p, -I_{n-p}).
+def hsvd_solve(ctx: Context, G, p: int | None = None, params: hsvd_params | None = None, *, jsig=None,
+               want_u=True, want_v=None, want_lambda=True, want_perm=True, out=None, check=True):
+    """Solves G = U Sigma V^T, V^T J V = J.
 
-    G: square float64 CUDA tensor.  Returns a dict with sigma, U, V, lambda,
-    perm (tensors or None), status and info (a dict).  ``out`` may hold
-    preallocated output tensors with the same keys."""
+    G: square float64 CUDA tensor.  J = diag(I_p, -I_{n-p}), or, with jsig (an
+    int8 CUDA tensor of +-1 entries, one per column of G, in any order), J =
+    diag(jsig) and p its number of +1 entries.  Returns a dict with sigma, U,
+    V, lambda, perm (tensors or None), status and info (a dict).  ``out`` may
+    hold preallocated output tensors with the same keys."""
     import torch
     L = lib()
     n = G.shape[0]
     assert G.shape == (n, n) and G.dtype == torch.float64 and G.is_cuda
+    if jsig is not None:
+        assert jsig.dtype == torch.int8 and jsig.numel() == n and jsig.is_cuda
+        jsig = jsig.contiguous()
+        if p is None:
+            p = int((jsig == 1).sum().item())
+    assert p is not None
     prm = params if params is not None else hsvd_default_params()
     if want_v is None:
         want_v = bool(prm.want_v)
@@ -222,7 +229,7 @@ def hsvd_solve(ctx: Context, G, p: int, params: hsvd_params | None = None, *, wa
     if want_perm and perm is None:
         perm = torch.empty(n, dtype=torch.int32, device=dev)
     info = hsvd_info()
-    st = L.hsvd_solve(ctx.handle, _ptr(Gc), lda, n, int(p), ctypes.byref(prm), _ptr(sigma),
+    st = L.hsvd_solve(ctx.handle, _ptr(Gc), lda, _ptr(jsig), n, int(p), ctypes.byref(prm), _ptr(sigma),
                       _ptr(U), U.stride(1) if U is not None else n, _ptr(V),
                       V.stride(1) if V is not None else n, _ptr(lam), _ptr(perm),
                       ctypes.byref(info))
@@ -239,40 +246,16 @@ def hsvd_autotune(ctx: Context, n: int):
     return a.value, w.value
 
 
-def hsvd_solve_j(ctx: Context, G, jsig, params: hsvd_params | None = None, *, check=True):
-    """As hsvd_solve with J's diagonal given in any order: jsig is an int8
-    CUDA tensor of +-1 entries, one per column of G."""
-    import torch
-    L = lib()
-    n = G.shape[0]
-    assert G.shape == (n, n) and G.dtype == torch.float64 and G.is_cuda
-    assert jsig.dtype == torch.int8 and jsig.numel() == n
-    prm = params if params is not None else hsvd_default_params()
-    Gc, lda = _colmajor(G)
-    dev = G.device
-    sigma = torch.empty(n, dtype=torch.float64, device=dev)
-    U = _new_colmajor(n, dev, torch.float64)
-    V = _new_colmajor(n, dev, torch.float64) if prm.want_v else None
-    lam = torch.empty(n, dtype=torch.float64, device=dev)
-    perm = torch.empty(n, dtype=torch.int32, device=dev)
-    info = hsvd_info()
-    st = L.hsvd_solve_j(ctx.handle, _ptr(Gc), lda, n, _ptr(jsig.contiguous()), ctypes.byref(prm),
-                        _ptr(sigma), _ptr(U), U.stride(1), _ptr(V), V.stride(1) if V is not None else n,
-                        _ptr(lam), _ptr(perm), ctypes.byref(info))
-    if check and st != OK:
-        raise HsvdError(st, "hsvd_solve_j")
-    return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, perm=perm, info=info.as_dict())
-
-
 def hsvd_solve_batched(ctx: Context, ns, ps, G_packed, offs, voffs, params: hsvd_params | None = None,
                        *, want_u=True, want_v=None, want_lambda=True, out=None, check=True):
     """Solves many independent problems in one call.
 
-    ns, ps, offs, voffs: host integer sequences (order, +1 signs, element
-    offset of each column-major G_k in G_packed, offset of sigma_k).
-    G_packed: float64 CUDA tensor with all inputs.  Returns a dict with the
-    packed outputs (sigma, U, V, lam: tensors or None), per-problem status and
-    sweeps (NumPy arrays) and the aggregate info."""
+    ns, ps, offs, voffs: integer sequences (order, +1 signs, element offset of
+    each column-major G_k in G_packed, offset of sigma_k), passed to the
+    library as device arrays.  G_packed: float64 CUDA tensor with all inputs.
+    Returns a dict with the packed outputs (sigma, U, V, lam: tensors or
+    None), the per-problem infos (a list of dicts) and, for convenience, their
+    statuses and FP64 sweep counts as NumPy arrays."""
     import numpy as np
     import torch
     L = lib()
@@ -280,12 +263,14 @@ def hsvd_solve_batched(ctx: Context, ns, ps, G_packed, offs, voffs, params: hsvd
     prm = params if params is not None else hsvd_default_params()
     if want_v is None:
         want_v = bool(prm.want_v)
-    n_a = np.ascontiguousarray(ns, dtype=np.int32)
-    p_a = np.ascontiguousarray(ps, dtype=np.int32)
-    o_a = np.ascontiguousarray(offs, dtype=np.int64)
-    v_a = np.ascontiguousarray(voffs, dtype=np.int64)
-    tot_v = int((v_a + n_a).max()) if batch else 0
     dev = G_packed.device
+    n_a = np.ascontiguousarray(ns, dtype=np.int32)
+    v_a = np.ascontiguousarray(voffs, dtype=np.int64)
+    n_d = torch.from_numpy(n_a).to(dev)
+    p_d = torch.from_numpy(np.ascontiguousarray(ps, dtype=np.int32)).to(dev)
+    o_d = torch.from_numpy(np.ascontiguousarray(offs, dtype=np.int64)).to(dev)
+    v_d = torch.from_numpy(v_a).to(dev)
+    tot_v = int((v_a + n_a).max()) if batch else 0
     out = dict(out or {})
     sigma = out.get("sigma")
     if sigma is None:
@@ -299,17 +284,15 @@ def hsvd_solve_batched(ctx: Context, ns, ps, G_packed, offs, voffs, params: hsvd
     lam = out.get("lambda") if want_lambda else None
     if want_lambda and lam is None:
         lam = torch.empty(tot_v, dtype=torch.float64, device=dev)
-    status = np.zeros(batch, dtype=np.int32)
-    sweeps = np.zeros(batch, dtype=np.int32)
-    info = hsvd_info()
-    c = lambda a: ctypes.c_void_p(a.ctypes.data)
-    st = L.hsvd_solve_batched(ctx.handle, batch, c(n_a), c(p_a), c(o_a), c(v_a), _ptr(G_packed),
-                              ctypes.byref(prm), _ptr(sigma), _ptr(U), _ptr(V), _ptr(lam), c(status),
-                              c(sweeps), ctypes.byref(info))
+    infos = (hsvd_info * max(batch, 1))()
+    st = L.hsvd_solve_batched(ctx.handle, batch, _ptr(n_d), _ptr(p_d), _ptr(o_d), _ptr(v_d), _ptr(G_packed),
+                              ctypes.byref(prm), _ptr(sigma), _ptr(U), _ptr(V), _ptr(lam), infos)
     if check and st != OK:
         raise HsvdError(st, "hsvd_solve_batched")
-    return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, statuses=status, sweeps=sweeps,
-                info=info.as_dict())
+    info_list = [infos[k].as_dict() for k in range(batch)]
+    status = np.array([i["status"] for i in info_list], dtype=np.int32)
+    sweeps = np.array([i["sweeps"] for i in info_list], dtype=np.int32)
+    return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, infos=info_list, statuses=status, sweeps=sweeps)
 
 
 def hsvd_pair_params(ctx: Context, aii, ajj, aij, hyp, tol: float, t_thresh: float, block=False):

@@ -32,18 +32,18 @@ def test_defaults_and_argument_checks_without_gpu():
     L = _lib_or_skip()
     prm = H.hsvd_default_params()
     assert (prm.precision, prm.algo, prm.ordering, prm.sort, prm.want_v, prm.max_sweeps,
-            prm.graph, prm.inner_sweeps) == (H.FP64, H.AUTO, H.MODMOD, 1, 1, 100, 1, 0)
+            prm.graph, prm.inner_sweeps, prm.reorth_accept) == (H.FP64, H.AUTO, H.MODMOD, 1, 1, 100, 1, 0, 0.0)
     assert H.hsvd_version().startswith("hsvd-gfx950")
     # argument errors are reported before any device call
     assert L.hsvd_init(None, 0, None) == H.E_INVAL
     assert L.hsvd_destroy(None) == H.E_INVAL
     info = H.hsvd_info()
-    assert L.hsvd_solve(None, None, 1, 1, 0, None, None, None, 1, None, 1, None, None,
+    assert L.hsvd_solve(None, None, 1, None, 1, 0, None, None, None, 1, None, 1, None, None,
                         ctypes.byref(info)) == H.E_INVAL
     assert L.hsvd_pivot_trace(None, 0, 4, 1, None) == H.E_INVAL
     assert L.hsvd_block_trace(None, 0, 64, 32, 1, None) == H.E_INVAL
     assert L.hsvd_solve_batched(None, 1, None, None, None, None, None, None, None, None, None, None,
-                                None, None, ctypes.byref(info)) == H.E_INVAL
+                                ctypes.byref(info)) == H.E_INVAL
     assert L.hsvd_block_pair_params(None, 1, None, None, None, None, 0.0, 0.0, None, None, None,
                                     None, None) == H.E_INVAL
 

@@ -97,7 +97,7 @@ def test_error_paths(hsvd_ctx):
 
 @pytest.mark.parametrize("n,algo", [(96, 1), (512, 2)])
 def test_signature_in_any_order(hsvd_ctx, n, algo):
-    """hsvd_solve_j with J's signs scattered over the columns equals hsvd_solve
+    """hsvd_solve with J's signs scattered over the columns (jsig) equals hsvd_solve
     on the stably partitioned matrix, mapped back; invariants with that J."""
     import torch
 
@@ -108,7 +108,7 @@ def test_signature_in_any_order(hsvd_ctx, n, algo):
     pi = np.r_[np.flatnonzero(j == 1), np.flatnonzero(j == -1)]
     p = int((j == 1).sum())
     prm = H.hsvd_default_params(algo=algo)
-    Rj = H.hsvd_solve_j(hsvd_ctx, torch.from_numpy(G).cuda(), torch.from_numpy(j).cuda(), prm)
+    Rj = H.hsvd_solve(hsvd_ctx, torch.from_numpy(G).cuda(), p, prm, jsig=torch.from_numpy(j).cuda())
     Rp = run_lib(hsvd_ctx, np.asfortranarray(G[:, pi]), p, algo=algo)
     sj, Uj, Vj = (Rj["sigma"].cpu().numpy(), Rj["U"].cpu().numpy(), Rj["V"].cpu().numpy())
     assert np.array_equal(sj[pi], Rp["sigma"])

@@ -73,14 +73,14 @@ def test_eigen_1056_spectrum(hsvd_ctx, precision):
 
 def test_eigen_jsig_unordered(hsvd_ctx):
     """The factor straight from the factorisation, signs in pivot order,
-    through hsvd_solve_j: same eigenvalues as the reordered solve."""
+    through hsvd_solve with jsig: same eigenvalues as the reordered solve."""
     import torch
 
     from paper_1008_1371_amd import hsvd as H
     n = 160
     G, jsig, lam, _ = W.indefinite(n)
-    R = H.hsvd_solve_j(hsvd_ctx, torch.from_numpy(np.array(G, order="F")).cuda(),
-                       torch.from_numpy(np.array(jsig)).cuda(), H.hsvd_default_params(algo=2))
+    R = H.hsvd_solve(hsvd_ctx, torch.from_numpy(np.array(G, order="F")).cuda(), None,
+                     H.hsvd_default_params(algo=2), jsig=torch.from_numpy(np.array(jsig)).cuda())
     got = np.sort(R["lam"].cpu().numpy())
     rel = np.abs(got - np.sort(lam)) / np.abs(np.sort(lam))
     say("eigen jsig", rel.max())

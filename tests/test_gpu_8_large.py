@@ -49,3 +49,7 @@ def test_colscaled8192_both_precisions(hsvd_ctx):
     ev = (torch.linalg.matrix_norm(V1 * flip - V0) / torch.linalg.matrix_norm(V0)).item()
     say("mixed vs fp64: sigma", es, "U", eu, "V", ev)
     assert es <= 1e-12
+    # two converged iterates of different trajectories: U and V agree to the
+    # level the stop rule leaves (off-diagonal up to tol = 8.2e-12 over the
+    # relative gaps of the spectrum; 2.1e-9 measured), not to 1e-12
+    assert eu <= 1e-7 and ev <= 1e-7, (eu, ev)
