@@ -20,7 +20,7 @@ struct hsvd_ctx {
     hipStream_t stream = nullptr;
     void *ws = nullptr;
     size_t ws_bytes = 0;
-    void *aux = nullptr;                     // buffers of hsvd_solve_j (outside the solver's workspace)
+    void *aux = nullptr;                     // buffers of a solve with jsig in any order, autotuner input
     size_t aux_bytes = 0;
     hsvd::Ctl *host_ctl = nullptr;           // pinned
     std::vector<hipEvent_t> events;          // reusable timing events

@@ -86,10 +86,18 @@ def _eig_errors(R, p, lam):
     return np.abs(got - want) / np.abs(want)
 
 
-# Relative accuracy of the computed eigenvalues: the oracle (pairwise and
-# block orderings) reaches 5-6 n u at n = 64 .. 416 on these inputs; 20 n u
-# is the gate used here and on the GPU.
-EIG_REL = 20
+# Relative accuracy of each computed eigenvalue: one gate, the rotation-count
+# bound.  A column takes part in about 2 rot / n of the solve's rot
+# rotations; their rounding errors add up like a random walk, so each
+# eigenvalue carries about sqrt(2 rot / n) roundings of its own size, times
+# the n u of one dot product over the column: 0.5 sqrt(rot / n) n u, and
+# never less than 10 n u.  The same bound holds the normwise eigenvalue
+# invariant of every solve (pins.check_invariants).  It binds within about
+# 2x for the pointwise method at n = 4096 (about 13 n^2 / 2 rotations; the
+# GPU test of that size), more loosely for the block orderings, which apply
+# fewer rotations.
+def eig_gate(n, rotations):
+    return max(10.0, 0.5 * np.sqrt(max(rotations, 0) / n)) * n * U64
 
 
 @pytest.mark.parametrize("n", [64, 160])
@@ -99,15 +107,16 @@ def test_oracle_eigenvalues_match_spectrum(n, block):
     R = oracle.hsvd(G, p, block=block)
     assert R["status"] == 0
     rel = _eig_errors(R, p, lam)
-    assert rel.max() <= EIG_REL * n * U64, rel.max()
+    gate = eig_gate(n, R["rotations"])
+    assert rel.max() <= gate, (rel.max(), gate)
     # the smallest eigenvalues (|lambda| ~ a 1e-5) are as accurate as the
     # largest: relative, not absolute, accuracy
     small = np.argsort(np.abs(np.sort(lam)))[: n // 8]
-    assert rel[small].max() <= EIG_REL * n * U64
+    assert rel[small].max() <= gate
 
 
 def test_oracle_eigen_planted_error_is_caught():
     """One sign of J flipped must fail the eigenvalue gate."""
     G, p, lam = W.eigen(64)
     R = oracle.hsvd(G, p + 1 if p < 64 else p - 1)  # wrong J
-    assert R["status"] != 0 or _eig_errors(R, p, lam).max() > EIG_REL * 64 * U64
+    assert R["status"] != 0 or _eig_errors(R, p, lam).max() > eig_gate(64, R["rotations"])
