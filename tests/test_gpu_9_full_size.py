@@ -13,8 +13,13 @@ Both converge through the stop rule of eq. (4.2) at tol = 1e-15 n, which
 leaves the off-diagonal level of the final Gram matrix at up to tol, so two
 converged iterates differ in U and V by about that level over the relative
 gaps of the spectrum; at n = 4096 that is far above 1e-12, for the oracle's
-own twins as for the library.  The gates are therefore:
-  sigma normwise                 <= 1e-12 (both paths);
+own twins as for the library.  The singular values move by that level too
+where they cluster: the oracle's two orderings differ by 5e-13 normwise at
+n = 4096 (tol = 4.1e-12).  The FP64 block path follows the oracle's
+trajectory; the mixed path takes its own (FP32 sweeps first) and is held to
+the spread between two trajectories, as for U and V.  The gates are:
+  sigma normwise, FP64 path      <= 1e-12;
+  sigma normwise, mixed path     <= max(1e-12, 10 x the oracle's ordering spread);
   sigma componentwise            <= max(1e-12, 10 x the oracle's largest spread);
   U and V over the sample        <= max(1e-12, 10 x the oracle's largest spread).
 """
@@ -104,8 +109,9 @@ def test_full_size_vs_oracle(hsvd_ctx, name, precision):
     say("   oracle spreads (twin / ordering, sampled columns)", sp, "full matrices:",
         {s: {k: fx["meta"][s][k] for k in ("sigma_norm", "sigma_max", "U", "V")}
          for s in ("twin", "ordering_spread")})
-    assert e["sigma_norm"] <= 1e-12, e
-    assert e["lam_norm"] <= 2e-12, e
+    sig_gate = 1e-12 if precision == 0 else max(1e-12, 10 * fx["meta"]["ordering_spread"]["sigma_norm"])
+    assert e["sigma_norm"] <= sig_gate, (e, sig_gate)
+    assert e["lam_norm"] <= 2 * sig_gate, e
     assert e["sigma_max"] <= max(1e-12, 10 * sp["sigma_max"]), (e, sp)
     gate = max(1e-12, 10 * max(sp["U"], sp["V"]))
     assert e["U"] <= gate and e["V"] <= gate, (e, sp)
