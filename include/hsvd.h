@@ -36,8 +36,15 @@ typedef enum {
     HSVD_E_RANK = -3,    /* zero column, or a hyperbolic pair with |tanh 2phi| >= 1
                             (G, or G J G^T, numerically rank deficient; Sec. 1)     */
     HSVD_E_NOMEM = -4,   /* workspace allocation failed                             */
-    HSVD_E_DEVICE = -5   /* a HIP runtime call failed                               */
+    HSVD_E_DEVICE = -5,  /* a HIP runtime call failed                               */
+    HSVD_E_SIZE = -6     /* hsvd_solve_noalloc: the solve needs more workspace than
+                            the fixed scratch array (HSVD_NOALLOC_BYTES) holds    */
 } hsvd_status;
+
+/* Size in bytes of the fixed device scratch array of hsvd_solve_noalloc (per
+   device, held from library load to process exit).  It holds the workspace of
+   a solve of order n <= 1024 on every path (FP64 pairwise or block, mixed). */
+#define HSVD_NOALLOC_BYTES (64u << 20)
 
 typedef enum { HSVD_FP64 = 0, HSVD_MIXED = 1 } hsvd_precision;
 typedef enum { HSVD_AUTO = 0, HSVD_PAIRWISE = 1, HSVD_BLOCK = 2 } hsvd_algo;
@@ -160,6 +167,29 @@ void hsvd_default_params(hsvd_params *prm);
 hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, const signed char *jsig, int n, int p,
                        const hsvd_params *prm, double *sigma, double *U, int ldu, double *V, int ldv,
                        double *lambda, int *perm, hsvd_info *info);
+
+/* hsvd_solve without device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Computes what hsvd_solve computes with jsig = NULL
+ * (J = diag(I_p, -I_{n-p})), the same arguments otherwise, by the same kernels
+ * and launches: the results are identical to hsvd_solve's for the same G and
+ * parameters.  Differences:
+ *  - The workspace is a fixed array of HSVD_NOALLOC_BYTES in device memory
+ *    that the library reserves per device; no hipMalloc, hipFree, event or
+ *    graph is created.  A solve whose workspace does not fit returns
+ *    HSVD_E_SIZE before launching anything (its size grows as 16 n^2 bytes
+ *    for FP64, about 54 n^2 for HSVD_MIXED; every path fits for n <= 1024).
+ *  - prm->graph is ignored (stream launches), and hsvd_info carries no times
+ *    (ms_total and kernel_ms are zero).
+ *  - Every call on one device uses that device's one array, whatever the
+ *    context: calls that overlap on one device (two host threads, or two
+ *    contexts on different streams) race and corrupt each other.  Calls on one
+ *    context are ordered by its stream, and each call initialises all of the
+ *    workspace it reads; the array keeps the last call's contents.
+ * Errors: as hsvd_solve, plus HSVD_E_SIZE.  Synchronises. */
+hsvd_status hsvd_solve_noalloc(hsvd_ctx *ctx, const double *G, int lda, int n, int p, const hsvd_params *prm,
+                               double *sigma, double *U, int ldu, double *V, int ldv, double *lambda, int *perm,
+                               hsvd_info *info);
 
 /* Batched solves: `batch` independent problems G_k (n[k] x n[k], 1 <= n[k] <= 1024,
  * J_k = diag(I_p[k], -I_{n[k]-p[k]})), each solved as by hsvd_solve with the block

@@ -10,6 +10,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -30,6 +31,36 @@ struct hsvd_ctx {
         int valid = 0, algo = 0, wg = 0;
     } tune[16];                              // autotuner choice per size bucket (log2 of n, rounded up)
 };
+
+// Fixed device scratch of hsvd_solve_noalloc: the workspace of one solve,
+// for callers that cannot allocate device memory.  Each device holds its own
+// copy for the life of the process.  Host code never names the array in a
+// device context: its device address comes from hipGetSymbolAddress, taken
+// once per device in hsvd_init (with that device current) and kept in
+// g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[HSVD_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `device` (looked up on
+// the first call for that device).  Null if the lookup failed.
+void *scratch_address(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[device] = ptr;
+    }
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
 
 namespace {
 
@@ -244,6 +275,11 @@ hsvd_status hsvd_init(hsvd_ctx **out, int device, void *hip_stream)
         return HSVD_E_DEVICE;
     }
     ctx->host_ctl = static_cast<Ctl *>(h);
+    if (!scratch_address(device)) {
+        hipHostFree(h);
+        delete ctx;
+        return HSVD_E_DEVICE;
+    }
     tune_load(ctx);
     *out = ctx;
     return HSVD_OK;
@@ -533,6 +569,7 @@ struct SolveMode {
     size_t ws_cap = 0;    // bytes available at ws
     bool timing = true;   // HIP events around the solve and sampled kernels (events are created on demand)
     bool graphs = true;   // prm.graph honoured (a captured graph is created per solve)
+    hsvd_status too_big = HSVD_E_NOMEM;  // returned when ws is set and the solve needs more than ws_cap
 };
 
 // hsvd_solve for J = diag(I_p, -I_{n-p}) (columns in canonical order).
@@ -600,7 +637,7 @@ hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int 
     hsvd_status s = HSVD_OK;
     void *base = mode.ws;
     if (base) {
-        if (L.bytes > mode.ws_cap) return HSVD_E_NOMEM;
+        if (L.bytes > mode.ws_cap) return mode.too_big;
     } else {
         s = ensure_ws(ctx, L.bytes);
         if (s != HSVD_OK) return s;
@@ -1023,6 +1060,27 @@ extern "C" hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, const
     HSVD_TRY(launch_scatter_outputs(st, dpi, n, sp, Up, Vp, lp, pmp, sigma, U, ldu, V, ldv, lambda, perm));
     HSVD_TRY(hipStreamSynchronize(st));
     return s;
+}
+
+extern "C" hsvd_status hsvd_solve_noalloc(hsvd_ctx *ctx, const double *G, int lda, int n, int p,
+                                          const hsvd_params *prm_in, double *sigma, double *U, int ldu, double *V,
+                                          int ldv, double *lambda, int *perm, hsvd_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    if (!ctx || !G || !sigma || n < 1 || p < 0 || p > n || lda < n) return HSVD_E_INVAL;
+    hsvd_params prm;
+    if (prm_in) prm = *prm_in;
+    else hsvd_default_params(&prm);
+    HSVD_TRY(hipSetDevice(ctx->device));
+    void *ptr = scratch_address(ctx->device);
+    if (!ptr) return HSVD_E_DEVICE;
+    SolveMode mode;
+    mode.ws = ptr;
+    mode.ws_cap = HSVD_NOALLOC_BYTES;
+    mode.timing = false;  // no events (created on demand otherwise)
+    mode.graphs = false;  // no graph capture (instantiation allocates)
+    mode.too_big = HSVD_E_SIZE;
+    return solve_canonical(ctx, G, lda, n, p, prm, sigma, U, ldu, V, ldv, lambda, perm, info, mode);
 }
 
 extern "C" hsvd_status hsvd_autotune(hsvd_ctx *ctx, int n, int *best_algo, int *best_wg)

@@ -19,9 +19,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhsvd.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "hsvd.h")
 
-OK, E_INVAL, E_NOCONV, E_RANK, E_NOMEM, E_DEVICE = 0, -1, -2, -3, -4, -5
+OK, E_INVAL, E_NOCONV, E_RANK, E_NOMEM, E_DEVICE, E_SIZE = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOCONV", -3: "E_RANK", -4: "E_NOMEM",
-                -5: "E_DEVICE"}
+                -5: "E_DEVICE", -6: "E_SIZE"}
+NOALLOC_BYTES = 64 << 20  # HSVD_NOALLOC_BYTES
 FP64, MIXED = 0, 1
 AUTO, PAIRWISE, BLOCK = 0, 1, 2
 MODMOD, ROUNDROBIN = 0, 1
@@ -99,10 +100,12 @@ def lib():
     L.hsvd_pivot_trace.argtypes = [vp, ip, ip, ip, vp]
     L.hsvd_sort_diag.argtypes = [vp, ip, ip, vp, vp]
     L.hsvd_block_trace.argtypes = [vp, ip, ip, ip, ip, vp]
+    L.hsvd_solve_noalloc.argtypes = [vp, vp, ip, ip, ip, ctypes.POINTER(hsvd_params), vp, vp, ip, vp, ip,
+                                     vp, vp, ctypes.POINTER(hsvd_info)]
     L.hsvd_solve_batched.argtypes = [vp, ip, vp, vp, vp, vp, vp, ctypes.POINTER(hsvd_params), vp, vp,
                                      vp, vp, vp]
     L.hsvd_version.restype = ctypes.c_char_p
-    for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_autotune",
+    for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_solve_noalloc", "hsvd_autotune",
                  "hsvd_pair_params",
                  "hsvd_block_pair_params",
                  "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_block_trace", "hsvd_solve_batched"):
@@ -189,7 +192,7 @@ def hsvd_default_params(**overrides) -> hsvd_params:
 
 
 def hsvd_solve(ctx: Context, G, p: int | None = None, params: hsvd_params | None = None, *, jsig=None,
-               want_u=True, want_v=None, want_lambda=True, want_perm=True, out=None, check=True):
+               want_u=True, want_v=None, want_lambda=True, want_perm=True, out=None, check=True, noalloc=False):
     """Solves G = U Sigma V^T, V^T J V = J.
 
     G: square float64 CUDA tensor.  J = diag(I_p, -I_{n-p}), or, with jsig (an
@@ -229,13 +232,27 @@ def hsvd_solve(ctx: Context, G, p: int | None = None, params: hsvd_params | None
     if want_perm and perm is None:
         perm = torch.empty(n, dtype=torch.int32, device=dev)
     info = hsvd_info()
-    st = L.hsvd_solve(ctx.handle, _ptr(Gc), lda, _ptr(jsig), n, int(p), ctypes.byref(prm), _ptr(sigma),
-                      _ptr(U), U.stride(1) if U is not None else n, _ptr(V),
-                      V.stride(1) if V is not None else n, _ptr(lam), _ptr(perm),
-                      ctypes.byref(info))
+    ldu = U.stride(1) if U is not None else n
+    ldv = V.stride(1) if V is not None else n
+    if noalloc:
+        assert jsig is None, "hsvd_solve_noalloc takes J = diag(I_p, -I_{n-p})"
+        name = "hsvd_solve_noalloc"
+        st = L.hsvd_solve_noalloc(ctx.handle, _ptr(Gc), lda, n, int(p), ctypes.byref(prm), _ptr(sigma), _ptr(U),
+                                  ldu, _ptr(V), ldv, _ptr(lam), _ptr(perm), ctypes.byref(info))
+    else:
+        name = "hsvd_solve"
+        st = L.hsvd_solve(ctx.handle, _ptr(Gc), lda, _ptr(jsig), n, int(p), ctypes.byref(prm), _ptr(sigma),
+                          _ptr(U), ldu, _ptr(V), ldv, _ptr(lam), _ptr(perm), ctypes.byref(info))
     if check and st not in (OK,):
-        raise HsvdError(st, "hsvd_solve")
+        raise HsvdError(st, name)
     return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, perm=perm, info=info.as_dict())
+
+
+def hsvd_solve_noalloc(ctx: Context, G, p: int, params: hsvd_params | None = None, **kw):
+    """hsvd_solve through the entry point that allocates no device memory
+    (the library's fixed scratch array; J = diag(I_p, -I_{n-p})).  Output
+    tensors are allocated here unless passed in ``out``."""
+    return hsvd_solve(ctx, G, p, params, noalloc=True, **kw)
 
 
 def hsvd_autotune(ctx: Context, n: int):

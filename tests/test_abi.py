@@ -18,7 +18,8 @@ def test_header_declares_the_entry_points():
     names = H.header_functions()
     for required in ("hsvd_init", "hsvd_destroy", "hsvd_default_params", "hsvd_solve",
                      "hsvd_pair_params", "hsvd_block_pair_params", "hsvd_pivot_trace",
-                     "hsvd_sort_diag", "hsvd_block_trace", "hsvd_solve_batched", "hsvd_version"):
+                     "hsvd_sort_diag", "hsvd_block_trace", "hsvd_solve_batched", "hsvd_version",
+                     "hsvd_solve_noalloc"):
         assert required in names
 
 
@@ -40,6 +41,8 @@ def test_defaults_and_argument_checks_without_gpu():
     info = H.hsvd_info()
     assert L.hsvd_solve(None, None, 1, None, 1, 0, None, None, None, 1, None, 1, None, None,
                         ctypes.byref(info)) == H.E_INVAL
+    assert L.hsvd_solve_noalloc(None, None, 1, 1, 0, None, None, None, 1, None, 1, None, None,
+                                ctypes.byref(info)) == H.E_INVAL
     assert L.hsvd_pivot_trace(None, 0, 4, 1, None) == H.E_INVAL
     assert L.hsvd_block_trace(None, 0, 64, 32, 1, None) == H.E_INVAL
     assert L.hsvd_solve_batched(None, 1, None, None, None, None, None, None, None, None, None, None,
