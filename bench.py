@@ -83,8 +83,8 @@ def parse():
                     help="target CPU time of the bounded oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--batched", type=int, default=0,
-                    help="also time the batched solver on this many small problems")
+    ap.add_argument("--batched", type=int, default=10000,
+                    help="also time the batched solver on this many small problems (0: skip)")
     ap.add_argument("--inner-sweeps", type=int, default=0,
                     help="block modes: 0 = block-oriented method; k > 0 = full-block method with at most "
                          "k inner sweeps per pivot block")
