@@ -328,8 +328,9 @@ def timed(H, ctx, G, p, prm, out, steps, warmup, check):
 
 
 def batched_line(H, W, ctx, count):
-    """The batched solver on `count` Gaussian problems, n ~ U{8..256}, FP64 and
-    mixed precision."""
+    """The batched solver on `count` Gaussian problems, n ~ U{8..256}, FP64
+    (one persistent launch, its width autotuned first) and mixed precision
+    (launches grouped by bordered order)."""
     import numpy as np
     import torch
     ns, ps, Gs = W.batch(count)
@@ -337,6 +338,9 @@ def batched_line(H, W, ctx, count):
     voffs = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
     Gd = torch.from_numpy(flat).cuda()
     out = {"problems": count, "n_range": [int(ns.min()), int(ns.max())]}
+    # the persistent kernel's width for this size mix (outside the timed runs)
+    best, widths = H.hsvd_autotune_batched(ctx, ns, ps)
+    out["persistent_width"] = {"threads": best, "autotune_ms": widths}
     for name, prec in (("fp64", H.FP64), ("mixed", H.MIXED)):
         prm = H.hsvd_default_params(precision=prec)
         H.hsvd_solve_batched(ctx, ns, ps, Gd, offs, voffs, prm)  # warm-up

@@ -81,6 +81,11 @@ typedef struct {
     double reorth_accept; /* mixed path: largest accepted max |J X^T J X - I| after the
                         Newton-Schulz J-re-orthogonalisation of V (above it the
                         solve restarts from G in FP64); <= 0: 16384 n u, u = 2^-53  */
+    int batch_mode;  /* hsvd_solve_batched: 0 = every FP64 block-oriented problem with
+                        n <= 256 in one persistent launch (the others, and mixed
+                        precision, in launches grouped by bordered order);
+                        1 = grouped launches for every problem.  The two give
+                        bit-identical results                                      */
 } hsvd_params;
 
 /* Kernel classes timed in hsvd_info (index into the kernel_* arrays). */
@@ -210,11 +215,18 @@ hsvd_status hsvd_solve_noalloc(hsvd_ctx *ctx, const double *G, int lda, int n, i
  *                    ldg, reorth_iters, reorth_resid, fp64_restart, rotations,
  *                    skips, active_pairs; ms_total is the device time of the
  *                    whole batched call; the kernel_* arrays are zero.
- * Problems are grouped by their bordered order (a multiple of 2b); each group
- * runs as one sequence of launches that covers all of its problems, with the
- * stop rule decided per problem on the device.  Returns HSVD_OK when every
- * problem converged, else the status of the first problem that did not.
- * Synchronises. */
+ * FP64 problems of the block-oriented method with n <= 256 run in one
+ * persistent launch (prm->batch_mode = 0, the default; captured as a HIP graph
+ * when prm->graph is set): each workgroup takes problems from a device work
+ * queue, largest n first, and solves each one completely -- Gram, inner
+ * rotations and update of every block pair, sort and the stop rule of
+ * eq. (4.2) per sweep, output extraction -- with no host round trip.  The
+ * other problems (n > 256, mixed precision, the full-block method, or
+ * batch_mode = 1) are grouped by their bordered order (a multiple of 2b); each
+ * group runs as one sequence of launches that covers all of its problems,
+ * with the stop rule decided per problem on the device.  Both forms give
+ * bit-identical results.  Returns HSVD_OK when every problem converged, else
+ * the status of the first problem that did not.  Synchronises. */
 hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n, const int *p, const long long *off,
                                const long long *voff, const double *G, const hsvd_params *prm, double *sigma,
                                double *U, double *V, double *lambda, hsvd_info *info);
@@ -232,6 +244,25 @@ hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n, const int
  *   best_algo, best_wg   host, may be NULL: the chosen path and workgroup target.
  * Errors: HSVD_E_INVAL (n < 2 or n > 16382).  Synchronises. */
 hsvd_status hsvd_autotune(hsvd_ctx *ctx, int n, int *best_algo, int *best_wg);
+
+/* Autotuner of the batched solver.  FP64 block-oriented problems with n <= 256
+ * run in one persistent launch in which each workgroup solves whole problems;
+ * its width (256, 512 or 1024 threads per problem: the inner rotations and the
+ * column updates of a block pair spread over all of them) is a speed-only
+ * choice.  This call times the three widths on a sample of at most 4096 of the
+ * given problems (every k-th, the ones with n <= 256; seeded synthetic entries,
+ * uniform in [-1, 1) from a counter-based hash; V accumulated) and keeps the
+ * fastest for the bucket of the sample's largest order ((0, 64], (64, 128],
+ * (128, 192], (192, 256]) in the context; later hsvd_solve_batched calls whose
+ * persistent problems fall in that bucket use it (default before tuning: 256).
+ * The results of a batched solve do not depend on the width (bit-identical).
+ * With HSVD_AUTOTUNE_CACHE set the choice is written to that file too.
+ *   n, p          device or host arrays of `batch` entries (as hsvd_solve_batched).
+ *   best_threads  host, may be NULL: the chosen width.
+ *   ms            host, may be NULL: 3 floats, the time of each width (ms).
+ * Errors: HSVD_E_INVAL (no problem with n <= 256, or bad n / p).  Synchronises. */
+hsvd_status hsvd_autotune_batched(hsvd_ctx *ctx, int batch, const int *n, const int *p, int *best_threads,
+                                  float *ms);
 
 /* ---- Diagnostics: the individual steps of the path on caller data ---- */
 

@@ -10,6 +10,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -30,6 +31,10 @@ struct hsvd_ctx {
     struct Tune {
         int valid = 0, algo = 0, wg = 0;
     } tune[16];                              // autotuner choice per size bucket (log2 of n, rounded up)
+    // threads per workgroup of the persistent batched kernel, by the bucket of
+    // the largest order in the launch ((0, 64], (64, 128], (128, 192],
+    // (192, 256]); 0 = the default
+    int persist_threads[4] = {0, 0, 0, 0};
 };
 
 // Fixed device scratch of hsvd_solve_noalloc: the workspace of one solve,
@@ -91,6 +96,13 @@ void tune_load(hsvd_ctx *ctx)
             ctx->tune[b].wg = w;
         }
     }
+    // {"batched_bucket": B, "threads": T}
+    for (const char *q = strstr(buf, "\"batched_bucket\""); q; q = strstr(q + 1, "\"batched_bucket\"")) {
+        int b = -1, t = 0;
+        if (sscanf(q, "\"batched_bucket\": %d, \"threads\": %d", &b, &t) == 2 && b >= 0 && b < 4 &&
+            (t == 256 || t == 512 || t == 1024))
+            ctx->persist_threads[b] = t;
+    }
 }
 
 void tune_save(const hsvd_ctx *ctx)
@@ -105,6 +117,11 @@ void tune_save(const hsvd_ctx *ctx)
         if (!ctx->tune[b].valid) continue;
         fprintf(f, "%s\n  {\"bucket\": %d, \"algo\": %d, \"wg\": %d}", first ? "" : ",", b, ctx->tune[b].algo,
                 ctx->tune[b].wg);
+        first = false;
+    }
+    for (int b = 0; b < 4; ++b) {
+        if (!ctx->persist_threads[b]) continue;
+        fprintf(f, "%s\n  {\"batched_bucket\": %d, \"threads\": %d}", first ? "" : ",", b, ctx->persist_threads[b]);
         first = false;
     }
     fprintf(f, "\n]}\n");
@@ -255,6 +272,8 @@ void hsvd_default_params(hsvd_params *prm)
     prm->t_thresh = 0.0;
     prm->graph = 1;
     prm->inner_sweeps = 0;
+    prm->reorth_accept = 0.0;
+    prm->batch_mode = 0;
 }
 
 hsvd_status hsvd_init(hsvd_ctx **out, int device, void *hip_stream)
@@ -1138,6 +1157,92 @@ extern "C" hsvd_status hsvd_autotune(hsvd_ctx *ctx, int n, int *best_algo, int *
     return HSVD_OK;
 }
 
+// Autotuner of the persistent batched kernel: the workgroup width (256, 512
+// or 1024 threads per problem) for the bucket of the largest order among the
+// given problems, timed on a sample of them with seeded synthetic entries.
+extern "C" hsvd_status hsvd_autotune_batched(hsvd_ctx *ctx, int batch, const int *n_in, const int *p_in,
+                                             int *best_threads, float *ms_out)
+{
+    if (!ctx || batch < 1 || !n_in || !p_in) return HSVD_E_INVAL;
+    HSVD_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    std::vector<int> n(batch), p(batch);
+    HSVD_TRY(hipMemcpyAsync(n.data(), n_in, sizeof(int) * batch, hipMemcpyDefault, st));
+    HSVD_TRY(hipMemcpyAsync(p.data(), p_in, sizeof(int) * batch, hipMemcpyDefault, st));
+    HSVD_TRY(hipStreamSynchronize(st));
+    // a sample of at most 4096 problems, every k-th, and only those the
+    // persistent kernel takes
+    const int stride = (batch + 4095) / 4096;
+    std::vector<int> sn, sp;
+    for (int k = 0; k < batch; k += stride) {
+        if (n[k] < 1 || n[k] > 1024 || p[k] < 0 || p[k] > n[k]) return HSVD_E_INVAL;
+        if (n[k] <= kPersistMaxOrder) {
+            sn.push_back(n[k]);
+            sp.push_back(p[k]);
+        }
+    }
+    if (sn.empty()) return HSVD_E_INVAL;
+    const int K = (int)sn.size();
+    int nmax = 0;
+    std::vector<long long> off(K), voff(K);
+    long long tot = 0, totv = 0;
+    for (int k = 0; k < K; ++k) {
+        off[k] = tot;
+        voff[k] = totv;
+        tot += (long long)sn[k] * sn[k];
+        totv += sn[k];
+        nmax = std::max(nmax, sn[k]);
+    }
+    size_t o = 0;
+    const size_t o_G = take_bytes(o, sizeof(double) * tot), o_U = take_bytes(o, sizeof(double) * tot);
+    const size_t o_V = take_bytes(o, sizeof(double) * tot), o_s = take_bytes(o, sizeof(double) * totv);
+    const hsvd_status sa = ensure_aux(ctx, o);
+    if (sa != HSVD_OK) return sa;
+    char *base = static_cast<char *>(ctx->aux);
+    double *G = reinterpret_cast<double *>(base + o_G);
+    for (int k = 0; k < K; ++k) HSVD_TRY(launch_synth(st, G + off[k], sn[k], 0xBA7C4ull + (unsigned long long)k));
+    // two events of its own, past the ones hsvd_solve_batched uses (handles,
+    // not pointers into the context's list, which that call may grow)
+    const size_t nev = 4 + 4 * 1024 / block_width();
+    hsvd_status se = ensure_events(ctx, nev + 2);
+    if (se != HSVD_OK) return se;
+    const hipEvent_t ev[2] = {ctx->events[nev], ctx->events[nev + 1]};
+    hsvd_params prm;
+    hsvd_default_params(&prm);
+    const int bucket = std::min(3, (nmax - 1) / 64);
+    const int saved = ctx->persist_threads[bucket];
+    const int cands[3] = {256, 512, 1024};
+    int best = kPersistDefaultThreads;
+    float best_ms = 1e30f;
+    for (int ci = 0; ci < 3; ++ci) {
+        ctx->persist_threads[bucket] = cands[ci];
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {  // the first run also warms up
+            HSVD_TRY(hipEventRecord(ev[0], st));
+            const hsvd_status s =
+                hsvd_solve_batched(ctx, K, sn.data(), sp.data(), off.data(), voff.data(), G, &prm,
+                                   reinterpret_cast<double *>(base + o_s), reinterpret_cast<double *>(base + o_U),
+                                   reinterpret_cast<double *>(base + o_V), nullptr, nullptr);
+            if (s != HSVD_OK && s != HSVD_E_NOCONV) {
+                ctx->persist_threads[bucket] = saved;
+                return s;
+            }
+            HSVD_TRY(hipEventRecord(ev[1], st));
+            HSVD_TRY(hipEventSynchronize(ev[1]));
+            HSVD_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        }
+        if (ms_out) ms_out[ci] = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cands[ci];
+        }
+    }
+    ctx->persist_threads[bucket] = best;
+    tune_save(ctx);
+    if (best_threads) *best_threads = best;
+    return HSVD_OK;
+}
+
 // FP32 phase of a batched mixed solve for one group, then the
 // J-re-orthogonalisation of each problem's V and G1 = G X -- the steps of a
 // single mixed solve, per problem.  FP32 block sweeps run until every problem
@@ -1256,6 +1361,136 @@ static hsvd_status batch_mixed_phase(hsvd_ctx *ctx, hipStream_t st, const BatchG
     return HSVD_OK;
 }
 
+// The problems `ids` (FP64, block-oriented, n <= kPersistMaxOrder) in one
+// persistent launch: a work queue of the problem indices, largest n first
+// (the longest solves start first; the short ones fill in at the end), one
+// workgroup slot of device memory per resident workgroup, per-problem results
+// read back into pinfo.  With prm.graph the queue reset and the launch are
+// captured and replayed as one graph.
+static hsvd_status batch_persistent(hsvd_ctx *ctx, hipStream_t st, const std::vector<int> &ids, const int *n,
+                                    const int *p, const long long *off, const long long *voff, const double *G,
+                                    const hsvd_params &prm, int max_sweeps, bool want_v, double *sigma, double *U,
+                                    double *V, double *lambda, std::vector<hsvd_info> &pinfo)
+{
+    const int K = (int)ids.size();
+    if (K == 0) return HSVD_OK;
+    const int batch = (int)pinfo.size();
+    int cus = 0;
+    HSVD_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    int nmax = 0;
+    for (int k : ids) nmax = std::max(nmax, n[k]);
+    const int bucket = std::min(3, (nmax - 1) / 64);
+    const int threads = ctx->persist_threads[bucket] ? ctx->persist_threads[bucket] : kPersistDefaultThreads;
+    const int per_cu = persist_blocks_per_cu(threads);
+    if (per_cu < 1 || cus < 1) return HSVD_E_DEVICE;
+    const int wgs = std::min(K, per_cu * cus);
+    // the work queue: problem indices by n, largest first (stable)
+    std::vector<int> order(ids);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return n[x] > n[y]; });
+    size_t o = 0;
+    const size_t o_order = take_bytes(o, sizeof(int) * K), o_next = take_bytes(o, sizeof(int));
+    const size_t o_n = take_bytes(o, sizeof(int) * batch), o_p = take_bytes(o, sizeof(int) * batch);
+    const size_t o_off = take_bytes(o, sizeof(long long) * batch), o_voff = take_bytes(o, sizeof(long long) * batch);
+    const size_t o_st = take_bytes(o, sizeof(int) * batch), o_sw = take_bytes(o, sizeof(int) * batch);
+    const size_t o_code = take_bytes(o, sizeof(int) * batch), o_mt = take_bytes(o, sizeof(double) * batch);
+    const size_t o_rot = take_bytes(o, sizeof(unsigned long long) * batch);
+    const size_t o_skip = take_bytes(o, sizeof(unsigned long long) * batch);
+    const size_t o_act = take_bytes(o, sizeof(unsigned long long) * batch);
+    const size_t o_slots = take_bytes(o, persist_slot_bytes() * (size_t)wgs);
+    hsvd_status s = ensure_ws(ctx, o);
+    if (s != HSVD_OK) return s;
+    char *base = static_cast<char *>(ctx->ws);
+    HSVD_TRY(hipMemcpyAsync(base + o_order, order.data(), sizeof(int) * K, hipMemcpyHostToDevice, st));
+    HSVD_TRY(hipMemcpyAsync(base + o_n, n, sizeof(int) * batch, hipMemcpyHostToDevice, st));
+    HSVD_TRY(hipMemcpyAsync(base + o_p, p, sizeof(int) * batch, hipMemcpyHostToDevice, st));
+    HSVD_TRY(hipMemcpyAsync(base + o_off, off, sizeof(long long) * batch, hipMemcpyHostToDevice, st));
+    HSVD_TRY(hipMemcpyAsync(base + o_voff, voff, sizeof(long long) * batch, hipMemcpyHostToDevice, st));
+    PersistArgs pa;
+    pa.batch = K;
+    pa.order = reinterpret_cast<int *>(base + o_order);
+    pa.next = reinterpret_cast<int *>(base + o_next);
+    pa.n = reinterpret_cast<int *>(base + o_n);
+    pa.p = reinterpret_cast<int *>(base + o_p);
+    pa.off = reinterpret_cast<long long *>(base + o_off);
+    pa.voff = reinterpret_cast<long long *>(base + o_voff);
+    pa.Gin = G;
+    pa.sigma = sigma;
+    pa.U = U;
+    pa.V = want_v ? V : nullptr;
+    pa.lambda = lambda;
+    pa.want_v = want_v ? 1 : 0;
+    pa.ordering = prm.ordering;
+    pa.sort = prm.sort ? 1 : 0;
+    pa.max_sweeps = max_sweeps;
+    pa.tol = prm.tol;
+    pa.tthresh = prm.t_thresh;
+    pa.status = reinterpret_cast<int *>(base + o_st);
+    pa.sweeps = reinterpret_cast<int *>(base + o_sw);
+    pa.code = reinterpret_cast<int *>(base + o_code);
+    pa.maxt = reinterpret_cast<double *>(base + o_mt);
+    pa.rot = reinterpret_cast<unsigned long long *>(base + o_rot);
+    pa.skip = reinterpret_cast<unsigned long long *>(base + o_skip);
+    pa.act = reinterpret_cast<unsigned long long *>(base + o_act);
+    pa.slots = base + o_slots;
+    if (prm.graph) {
+        if (!ctx->cap) HSVD_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+        if (!ctx->join) HSVD_TRY(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
+        hipStream_t q = ctx->cap;
+        HSVD_TRY(hipEventRecord(ctx->join, st));
+        HSVD_TRY(hipStreamWaitEvent(q, ctx->join, 0));
+        HSVD_TRY(hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal));
+        const hipError_t le = launch_batch_persist(q, pa, threads, wgs);
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(q, &graph);
+        if (le != hipSuccess || ee != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return HSVD_E_DEVICE;
+        }
+        hipGraphExec_t exec = nullptr;
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(graph);
+            return HSVD_E_DEVICE;
+        }
+        const hipError_t ge = hipGraphLaunch(exec, q);
+        hipError_t je = hipEventRecord(ctx->join, q);
+        if (je == hipSuccess) je = hipStreamWaitEvent(st, ctx->join, 0);
+        const hipError_t se = hipStreamSynchronize(st);
+        hipGraphExecDestroy(exec);
+        hipGraphDestroy(graph);
+        if (ge != hipSuccess || je != hipSuccess || se != hipSuccess) return HSVD_E_DEVICE;
+    } else {
+        HSVD_TRY(launch_batch_persist(st, pa, threads, wgs));
+    }
+    std::vector<int> hs(batch), hsw(batch), hc(batch);
+    std::vector<double> hm(batch);
+    std::vector<unsigned long long> hr(batch), hk(batch), ha(batch);
+    HSVD_TRY(hipMemcpyAsync(hs.data(), pa.status, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+    HSVD_TRY(hipMemcpyAsync(hsw.data(), pa.sweeps, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+    HSVD_TRY(hipMemcpyAsync(hc.data(), pa.code, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+    HSVD_TRY(hipMemcpyAsync(hm.data(), pa.maxt, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+    HSVD_TRY(hipMemcpyAsync(hr.data(), pa.rot, sizeof(unsigned long long) * batch, hipMemcpyDeviceToHost, st));
+    HSVD_TRY(hipMemcpyAsync(hk.data(), pa.skip, sizeof(unsigned long long) * batch, hipMemcpyDeviceToHost, st));
+    HSVD_TRY(hipMemcpyAsync(ha.data(), pa.act, sizeof(unsigned long long) * batch, hipMemcpyDeviceToHost, st));
+    HSVD_TRY(hipStreamSynchronize(st));
+    const int b = block_width();
+    for (int k : ids) {
+        hsvd_info &pi = pinfo[k];
+        const int r = (n[k] + 2 * b - 1) / (2 * b) * (2 * b), nb = r / b;
+        pi.status = hs[k];
+        pi.sweeps = hsw[k];
+        pi.code = hc[k];
+        pi.r = r;
+        pi.block = b;
+        pi.ldg = r;
+        pi.max_t_last = hm[k];
+        pi.rotations = (long long)hr[k];
+        pi.skips = (long long)hk[k];
+        pi.steps = (long long)hsw[k] * (prm.ordering == HSVD_ORD_MODMOD ? nb : nb - 1);
+        pi.active_pairs = (long long)ha[k];
+    }
+    return HSVD_OK;
+}
+
 extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n_in, const int *p_in,
                                           const long long *off_in, const long long *voff_in, const double *G,
                                           const hsvd_params *prm_in, double *sigma, double *U, double *V,
@@ -1272,6 +1507,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
     if (prm.ordering != HSVD_ORD_MODMOD && prm.ordering != HSVD_ORD_ROUNDROBIN) return HSVD_E_INVAL;
     if (prm.block != 0 && prm.block != block_width()) return HSVD_E_INVAL;
     if (prm.inner_sweeps < 0 || prm.inner_sweeps > 100) return HSVD_E_INVAL;
+    if (prm.batch_mode != 0 && prm.batch_mode != 1) return HSVD_E_INVAL;
     const bool want_v = prm.want_v != 0;
     if (V && !want_v) return HSVD_E_INVAL;
     // the mixed path carries V through its FP32 phase even when it is not returned
@@ -1295,14 +1531,26 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
     if (s != HSVD_OK) return s;
     hipEvent_t *ev = ctx->events.data();
 
-    // group the problems by bordered order r = n rounded up to 2b
+    // FP64 block-oriented problems with n <= kPersistMaxOrder: one persistent
+    // launch (batch_mode 0); the others grouped by bordered order r = n
+    // rounded up to 2b, one sequence of launches per group
+    std::vector<int> pers;
     std::vector<std::vector<int>> groups(1024 / (2 * b) + 1);
-    for (int k = 0; k < batch; ++k) groups[(n[k] + 2 * b - 1) / (2 * b)].push_back(k);
+    const bool persist_ok = !mixed && prm.inner_sweeps == 0 && prm.batch_mode == 0;
+    for (int k = 0; k < batch; ++k) {
+        if (persist_ok && n[k] <= kPersistMaxOrder)
+            pers.push_back(k);
+        else
+            groups[(n[k] + 2 * b - 1) / (2 * b)].push_back(k);
+    }
 
     // per-problem results, filled group by group
     std::vector<hsvd_info> pinfo(batch);
     memset(pinfo.data(), 0, sizeof(hsvd_info) * batch);
     HSVD_TRY(hipEventRecord(ev[0], st));
+    s = batch_persistent(ctx, st, pers, n.data(), p.data(), off.data(), voff.data(), G, prm, max_sweeps, want_v, sigma,
+                         U, V, lambda, pinfo);
+    if (s != HSVD_OK) return s;
     for (size_t gi = 1; gi < groups.size(); ++gi) {
         const std::vector<int> &ids = groups[gi];
         if (ids.empty()) continue;

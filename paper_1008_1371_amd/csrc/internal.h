@@ -450,6 +450,35 @@ hipError_t launch_batch_ns_accept(hipStream_t st, const BatchGroup &g, const Bat
 hipError_t launch_batch_copy_if(hipStream_t st, const BatchGroup &g, const double *src, double *dst,
                                 const int *flag, bool invert);
 
+// Batched solves in one persistent launch (batch_persist.hip): FP64,
+// block-oriented method, problems with n <= kPersistMaxOrder.  Workgroups
+// take problems from a work queue (order[], counter *next) and solve each one
+// completely; per-problem results go to status / sweeps / code / maxt / rot /
+// skip / act, indexed by problem.  slots: one slot of persist_slot_bytes()
+// per workgroup.
+constexpr int kPersistMaxOrder = 256;
+constexpr int kPersistDefaultThreads = 256;  // before the autotuner has chosen
+struct PersistArgs {
+    int batch = 0;
+    const int *order = nullptr;  // problem indices, largest n first
+    int *next = nullptr;         // work counter (zeroed by the launcher)
+    const int *n = nullptr, *p = nullptr;
+    const long long *off = nullptr, *voff = nullptr;
+    const double *Gin = nullptr;
+    double *sigma = nullptr, *U = nullptr, *V = nullptr, *lambda = nullptr;
+    int want_v = 1, ordering = 0, sort = 1, max_sweeps = 100;
+    double tol = 0.0, tthresh = 0.0;  // <= 0: 1e-15 n and sqrt(tol) / 2 per problem
+    int *status = nullptr, *sweeps = nullptr, *code = nullptr;
+    double *maxt = nullptr;
+    unsigned long long *rot = nullptr, *skip = nullptr, *act = nullptr;
+    char *slots = nullptr;
+};
+size_t persist_slot_bytes();
+// threads per workgroup: 256, 512 or 1024 (the block pair's inner solve and
+// update spread over all of them); 0 for another count
+int persist_blocks_per_cu(int threads);
+hipError_t launch_batch_persist(hipStream_t st, const PersistArgs &pa, int threads, int workgroups);
+
 // mixed path helpers
 hipError_t launch_to_fp32(hipStream_t st, const double *G, float *G32, float *V32, int ldg, int r);
 hipError_t launch_promote(hipStream_t st, const float *X32, double *X, int ldg, int r);

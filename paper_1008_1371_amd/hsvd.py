@@ -33,7 +33,8 @@ class hsvd_params(ctypes.Structure):
                 ("block", ctypes.c_int), ("sort", ctypes.c_int), ("want_v", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("tol", ctypes.c_double),
                 ("t_thresh", ctypes.c_double), ("graph", ctypes.c_int),
-                ("inner_sweeps", ctypes.c_int), ("reorth_accept", ctypes.c_double)]
+                ("inner_sweeps", ctypes.c_int), ("reorth_accept", ctypes.c_double),
+                ("batch_mode", ctypes.c_int)]
 
 
 NKERNELS = 8
@@ -104,11 +105,13 @@ def lib():
                                      vp, vp, ctypes.POINTER(hsvd_info)]
     L.hsvd_solve_batched.argtypes = [vp, ip, vp, vp, vp, vp, vp, ctypes.POINTER(hsvd_params), vp, vp,
                                      vp, vp, vp]
+    L.hsvd_autotune_batched.argtypes = [vp, ip, vp, vp, ctypes.POINTER(ip), vp]
     L.hsvd_version.restype = ctypes.c_char_p
     for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_solve_noalloc", "hsvd_autotune",
                  "hsvd_pair_params",
                  "hsvd_block_pair_params",
-                 "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_block_trace", "hsvd_solve_batched"):
+                 "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_block_trace", "hsvd_solve_batched",
+                 "hsvd_autotune_batched"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -261,6 +264,21 @@ def hsvd_autotune(ctx: Context, n: int):
     w = ctypes.c_int()
     _check(lib().hsvd_autotune(ctx.handle, int(n), ctypes.byref(a), ctypes.byref(w)), "hsvd_autotune")
     return a.value, w.value
+
+
+def hsvd_autotune_batched(ctx: Context, ns, ps):
+    """Times the persistent batched kernel's widths (256 / 512 / 1024 threads
+    per problem) on a sample of the given orders and keeps the fastest for
+    their size bucket; returns (threads, {threads: ms})."""
+    import numpy as np
+    n_a = np.ascontiguousarray(ns, dtype=np.int32)
+    p_a = np.ascontiguousarray(ps, dtype=np.int32)
+    best = ctypes.c_int()
+    ms = (ctypes.c_float * 3)()
+    _check(lib().hsvd_autotune_batched(ctx.handle, int(n_a.size), n_a.ctypes.data_as(ctypes.c_void_p),
+                                       p_a.ctypes.data_as(ctypes.c_void_p), ctypes.byref(best), ms),
+           "hsvd_autotune_batched")
+    return best.value, {256: ms[0], 512: ms[1], 1024: ms[2]}
 
 
 def hsvd_solve_batched(ctx: Context, ns, ps, G_packed, offs, voffs, params: hsvd_params | None = None,

@@ -149,3 +149,100 @@ def test_batched_mixed_edge_and_no_v(hsvd_ctx):
     R2, res2 = _run(hsvd_ctx, ns, ps, Gs, precision=1, want_v=0)
     for k in (0, 1, 2, 4):
         assert np.allclose(np.sort(res2[k]["sigma"]), np.sort(res[k]["sigma"]), rtol=1e-12, atol=0)
+
+
+def _packed(R):
+    out = {}
+    for k in ("sigma", "lam", "U", "V"):
+        out[k] = R[k].cpu().numpy() if R[k] is not None else None
+    return out
+
+
+@pytest.mark.parametrize("ordering,want_v", [("modmod", 1), ("roundrobin", 1), ("modmod", 0)])
+def test_batched_persistent_equals_grouped(hsvd_ctx, ordering, want_v):
+    """FP64 problems with n <= 256 run in one persistent launch (batch_mode 0)
+    or in launches grouped by bordered order (batch_mode 1): the same building
+    blocks with the same arithmetic in the same order, so the results are
+    bit-identical, statuses and counters included.  Mixed with problems above
+    256 (grouped in both modes) and a rank failure."""
+    from paper_1008_1371_amd import hsvd as H
+    ns, ps, Gs = W.batch(120, seed_sizes=81, seed_g=9300)
+    g = np.random.Generator(np.random.PCG64(12))
+    for n in (300, 257):
+        Gs.append(g.standard_normal((n, n)))
+    ns = np.r_[ns, [300, 257]].astype(np.int32)
+    ps = np.r_[ps, [100, 257]].astype(np.int32)
+    Gs[5] = Gs[5].copy()
+    Gs[5][:, 0] = 0.0  # rank failure in one problem only
+    o = H.MODMOD if ordering == "modmod" else H.ROUNDROBIN
+    outs = []
+    for mode in (0, 1):
+        R, _ = _run(hsvd_ctx, ns, ps, Gs, ordering=o, want_v=want_v, batch_mode=mode)
+        outs.append((R, _packed(R)))
+    (R0, P0), (R1, P1) = outs
+    say("persistent vs grouped", ordering, "want_v", want_v, "statuses", np.bincount(R0["statuses"] + 3))
+    assert np.array_equal(R0["statuses"], R1["statuses"])
+    assert R0["statuses"][5] == -3 and (np.delete(R0["statuses"], 5) == 0).all()
+    for key in ("sweeps", "rotations", "skips", "steps", "active_pairs", "code", "r", "ldg", "block"):
+        a = [i[key] for i in R0["infos"]]
+        b = [i[key] for i in R1["infos"]]
+        assert a == b, key
+    for k in ("sigma", "lam", "U", "V"):
+        if P0[k] is None:
+            assert P1[k] is None
+            continue
+        ok = np.isfinite(P1[k])
+        assert np.array_equal(P0[k][ok], P1[k][ok]), k
+
+
+@pytest.mark.timeout(600)
+def test_batched_persistent_full_size_matches_grouped(hsvd_ctx):
+    """The 10^4-problem workload (n ~ U{8..256}) through both modes: the
+    persistent launch reproduces the grouped launches bit for bit."""
+    from paper_1008_1371_amd import hsvd as H
+    ns, ps, Gs = W.batch(10000)
+    P = []
+    for mode in (0, 1):
+        R, _ = _run(hsvd_ctx, ns, ps, Gs, batch_mode=mode)
+        assert R["status"] == 0
+        P.append((R, _packed(R)))
+        say("mode", mode, "ms", R["infos"][0]["ms_total"], "max sweeps", int(R["sweeps"].max()))
+    assert np.array_equal(P[0][0]["sweeps"], P[1][0]["sweeps"])
+    for k in ("sigma", "lam", "U", "V"):
+        assert np.array_equal(P[0][1][k], P[1][1][k]), k
+
+
+def test_batched_persistent_widths_bit_identical(tmp_path, monkeypatch):
+    """The persistent kernel's workgroup width (256, 512 or 1024 threads per
+    problem; the autotuner's choice, fixed here through the tuning cache that
+    a new context reads) does not change the results: each width reproduces
+    the grouped launches bit for bit.  Then the autotuner picks one of the
+    three for this batch's size bucket."""
+    from paper_1008_1371_amd import hsvd as H
+    ns, ps, Gs = W.batch(64, seed_sizes=83, seed_g=9400)
+    ns[0] = 256  # the batch's largest order sets the bucket (192, 256]
+    Gs[0] = np.random.Generator(np.random.PCG64(3)).standard_normal((256, 256))
+    ref = None
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("HSVD_AUTOTUNE_CACHE", str(cache))
+    for threads in (None, 256, 512, 1024):
+        if threads is not None:
+            cache.write_text('{"entries": [{"batched_bucket": 3, "threads": %d}]}' % threads)
+        with H.Context(0) as ctx:
+            R, _ = _run(ctx, ns, ps, Gs, batch_mode=0 if threads else 1)
+            P = _packed(R)
+        assert R["status"] == 0
+        if ref is None:
+            ref = (R, P)
+            continue
+        say("width", threads, "bit-identical to grouped")
+        assert np.array_equal(R["sweeps"], ref[0]["sweeps"])
+        for k in ("sigma", "lam", "U", "V"):
+            assert np.array_equal(P[k], ref[1][k]), (threads, k)
+    cache.unlink()
+    with H.Context(0) as ctx:
+        best, ms = H.hsvd_autotune_batched(ctx, ns, ps)
+        say("autotune widths (ms)", ms, "best", best)
+        assert best in (256, 512, 1024) and all(v > 0 for v in ms.values())
+        assert best == min(ms, key=ms.get)
+        assert '"threads": %d' % best in cache.read_text()
