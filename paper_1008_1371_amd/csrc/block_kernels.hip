@@ -26,8 +26,15 @@
 //
 // The kernels are templated on the storage type T of G, V, the partial Grams
 // and W: double for the FP64 path, float for the FP32 sweeps of the mixed
-// path (FP32 MFMA with FP32 accumulation).  The inner solve always runs in
-// FP64 on the promoted Gram matrix; W is rounded to T for the update.
+// path (FP32 MFMA with FP32 accumulation).  The partial Grams are summed in
+// FP64.  The circle kernel holds A_P and W in FP64 and rounds W to T on
+// output; the cross kernel holds its blocks of A_P and W in T and computes
+// each rotation's parameters in FP64 from the T-held pivots, applying them in
+// T.
+//
+// The bodies of the Gram, the inner solves and the update are device
+// functions in block_device.h (shared with the persistent batched kernel);
+// the kernels here bind a launch's block indices to them.
 #include "block_device.h"
 
 namespace hsvd {
