@@ -60,7 +60,9 @@ typedef struct {
     int algo;        /* hsvd_algo                                                        */
     int ordering;    /* hsvd_ordering: modified modulus (Sec. 2, Algs. 4.3-4.4) or the
                         round-robin circle method starting on the same antidiagonal      */
-    int block;       /* block width b of the block path: 0 or 32                          */
+    int block;       /* block width b of the block path: 0 or 32; or 64 (FP64 single solves
+                        only: the wide block path, Gram and update on the FP64 MFMA GEMM,
+                        working copies in sorted position order)                        */
     int sort;        /* 1: sort the diagonal before sweep 0 and after every sweep (Alg. 4.1) */
     int want_v;      /* 1: accumulate V (V^{-T} of the paper, eq. 2.1)                   */
     int max_sweeps;  /* <= 0: 100                                                        */
@@ -297,7 +299,7 @@ hsvd_status hsvd_pivot_trace(hsvd_ctx *ctx, int ordering, int r, int steps, int 
 /* Block-path pivot positions of `steps` consecutive outer steps from the
  * start of sweep 0 (outer ordering over nb = r/b blocks; inner ordering of
  * each block pair as used by the solver).
- *   r, b       r a multiple of 2b; b = 32 (the block width the library runs).
+ *   r, b       r a multiple of 2b; b = 32 or 64 (the block widths the library runs).
  *   pairs      device ints out, concatenated over the steps: step s contributes
  *              (nb/2) x inner(s) x b pairs (i, j), i < j, ordered by block pair,
  *              inner step, slot; inner(s) = 2b - 1 at the first step of a sweep,

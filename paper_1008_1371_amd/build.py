@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libhsvd.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.hip", "pair_kernels.hip", "block_kernels.hip", "mixed_kernels.hip", "batch_kernels.hip",
-           "gemm_kernels.hip", "batch_persist.hip"]
+           "gemm_kernels.hip", "batch_persist.hip", "wide_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

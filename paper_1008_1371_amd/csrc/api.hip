@@ -179,6 +179,14 @@ Layout make_layout(int n, int r, int ldg, bool want_v, int pairs, int splits, in
     L.off_W32 = take(mixed ? sizeof(float) * (size_t)pairs * bb * 2 : 0);
     L.off_T1 = take(mixed ? sizeof(double) * mat : 0);
     L.off_T2 = take(mixed ? sizeof(double) * mat : 0);
+    const bool wide = b2 == 2 * kWideB;
+    L.wide = wide;
+    L.off_G2 = take(wide ? sizeof(double) * mat : 0);
+    L.off_V2 = take(wide && want_v ? sizeof(double) * mat : 0);
+    L.off_blk = take(wide ? sizeof(int2) * (size_t)pairs : 0);
+    L.off_pl = take(wide ? sizeof(int) * (size_t)r : 0);
+    L.off_rho2 = take(wide ? sizeof(int) * (size_t)r : 0);
+    L.off_wact = take(wide ? sizeof(int) * (size_t)pairs : 0);
     L.bytes = o;
     return L;
 }
@@ -214,6 +222,14 @@ Workspace carve(void *base, const Layout &L)
         w.W32 = reinterpret_cast<float *>(b + L.off_W32);
         w.T1 = L.off_T2 > L.off_T1 ? reinterpret_cast<double *>(b + L.off_T1) : nullptr;
         w.T2 = L.bytes > L.off_T2 ? reinterpret_cast<double *>(b + L.off_T2) : nullptr;
+    }
+    if (L.wide) {
+        w.G2 = reinterpret_cast<double *>(b + L.off_G2);
+        w.V2 = L.off_blk > L.off_V2 ? reinterpret_cast<double *>(b + L.off_V2) : nullptr;
+        w.blk = reinterpret_cast<int2 *>(b + L.off_blk);
+        w.pl = reinterpret_cast<int *>(b + L.off_pl);
+        w.rho2 = reinterpret_cast<int *>(b + L.off_rho2);
+        w.wact = reinterpret_cast<int *>(b + L.off_wact);
     }
     return w;
 }
@@ -516,6 +532,147 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
     return HSVD_OK;
 }
 
+// FP64 sweeps of the wide block path (b = 64): working copies in position
+// order (gathered from the input order after the first sort, moved after
+// every later sort), Gram and update on the block-pair form of the FP64 MFMA
+// GEMM, inner rotations in wide_inner_kernel.  On return, out_G / out_V /
+// out_rho hold G and V in the input's column order and rho, as finalize reads
+// them.  Kernel times as block_sweeps (first step of each sweep and every
+// kTimeEvery-th step after it timed).
+hsvd_status wide_sweeps(hsvd_ctx *ctx, const Workspace &w, int r, int p, int ldg, int nb, int splits, int ordering,
+                        bool want_v, bool sort, double tol, double tthresh, int inner_sweeps, int max_sweeps,
+                        bool timing, double *kms, long long *klaunch, long long *ktimed, int &sweeps,
+                        long long &steps, SweepResult &last, bool &finished, double *&out_G, double *&out_V,
+                        int *&out_rho)
+{
+    hipStream_t st = ctx->stream;
+    const int pairs = nb / 2, b2 = 2 * kWideB;
+    const int steps_per_sweep = ordering == HSVD_ORD_MODMOD ? nb : nb - 1;
+    double *Gc = w.G2, *Gn = w.G, *Vc = want_v ? w.V2 : nullptr, *Vn = want_v ? w.V : nullptr;
+    int *rc = w.rho, *rn = w.rho2;
+    // to position order: column q <- input column rho[q]
+    HSVD_TRY(launch_wide_move(st, w.G, Gc, ldg, r, w.rho, false, nullptr, nullptr));
+    if (want_v) HSVD_TRY(launch_wide_move(st, w.V, Vc, ldg, r, w.rho, false, nullptr, nullptr));
+    GemmArgs gram;  // partial[pair][split] = G_P(rows of split)^T G_P(rows of split)
+    gram.B = nullptr;
+    gram.C = w.P;
+    gram.M = gram.N = b2;
+    gram.K = ldg / splits;
+    gram.ldb = gram.lda = ldg;
+    gram.ldc = b2;
+    gram.sc = (long long)b2 * b2;
+    gram.blk = w.blk;
+    gram.bw = kWideB;
+    gram.map = 1 | 2;
+    gram.ksplit = splits;
+    GemmArgs upd;  // [G_P | V_P] <- [G_P | V_P] W, in place, pairs with a rotation only
+    upd.M = ldg;
+    upd.N = upd.K = b2;
+    upd.lda = upd.ldc = ldg;
+    upd.ldb = b2;
+    upd.B = w.W;
+    upd.sb = (long long)b2 * b2;
+    upd.blk = w.blk;
+    upd.bw = kWideB;
+    upd.map = 1 | 4;
+    upd.flag = w.wact;
+    upd.want = 1;
+    WideArgs wa;
+    wa.partial = w.P;
+    wa.splits = splits;
+    wa.W = w.W;
+    wa.blk = w.blk;
+    wa.p = p;
+    wa.tol = tol;
+    wa.tthresh = tthresh;
+    wa.inner_sweeps = inner_sweeps;
+    wa.active = w.wact;
+    wa.C = w.C;
+    wa.nrot = w.nrot;
+    wa.nskip = w.nskip;
+    wa.nact = w.nact;
+    wa.ntc = w.ntc;
+    wa.maxt = w.maxt;
+    wa.ctl = w.ctl;
+    hipEvent_t *ev = timing ? ctx->events.data() : nullptr;
+    finished = false;
+    long long gstep = 0;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+        double first[3] = {0.0, 0.0, 0.0}, rest[3] = {0.0, 0.0, 0.0};
+        int nrest = 0;
+        for (int k = 0; k < steps_per_sweep; ++k, ++gstep) {
+            const int par = (int)(gstep & 1);
+            const bool tm = timing && k % kTimeEvery == 0;
+            hipEvent_t *e = tm ? ev + 4 + 4 * k : nullptr;
+            HSVD_TRY(launch_wide_blk(st, ordering, nb, k, w.S2 + par * pairs, w.S2 + (par ^ 1) * pairs, w.blk));
+            if (tm) HSVD_TRY(hipEventRecord(e[0], st));
+            gram.A = gram.B = Gc;
+            HSVD_TRY(launch_gemm(st, gram, pairs * splits, true, false, true));
+            if (tm) HSVD_TRY(hipEventRecord(e[1], st));
+            wa.first = k == 0 ? 1 : 0;
+            HSVD_TRY(launch_wide_inner(st, wa, pairs));
+            if (tm) HSVD_TRY(hipEventRecord(e[2], st));
+            upd.A = Gc;
+            upd.C = Gc;
+            HSVD_TRY(launch_gemm(st, upd, pairs, false, false, false));
+            if (want_v) {
+                upd.A = Vc;
+                upd.C = Vc;
+                HSVD_TRY(launch_gemm(st, upd, pairs, false, false, false));
+            }
+            if (tm) HSVD_TRY(hipEventRecord(e[3], st));
+        }
+        for (int q = 0; q < 3; ++q) klaunch[HSVD_K_BLOCK_GRAM + q] += steps_per_sweep;
+        steps += steps_per_sweep;
+        // the kept diagonal (fresh norms, by position), the sort and the column moves
+        HSVD_TRY(launch_wide_iota(st, w.pl, r));
+        HSVD_TRY(launch_colnorm_pos<double>(st, Gc, ldg, w.pl, w.d, r));
+        if (sort) {
+            HSVD_TRY(launch_sort(st, w.d, w.pl, w.dtmp, w.rtmp, r, p));  // pl: the old position now at q
+            HSVD_TRY(launch_wide_move(st, Gc, Gn, ldg, r, w.pl, false, rc, rn));
+            if (want_v) HSVD_TRY(launch_wide_move(st, Vc, Vn, ldg, r, w.pl, false, nullptr, nullptr));
+            std::swap(Gc, Gn);
+            std::swap(Vc, Vn);
+            std::swap(rc, rn);
+        }
+        HSVD_TRY(launch_sweep_reduce(st, w, pairs));
+        HSVD_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HSVD_TRY(hipStreamSynchronize(st));
+        if (timing) {
+            for (int k = 0; k < steps_per_sweep; k += kTimeEvery) {
+                hipEvent_t *e = ev + 4 + 4 * k;
+                for (int q = 0; q < 3; ++q) {
+                    float ms = 0.f;
+                    HSVD_TRY(hipEventElapsedTime(&ms, e[q], e[q + 1]));
+                    (k == 0 ? first : rest)[q] += ms;
+                }
+                if (k > 0) ++nrest;
+            }
+            const double scale = nrest > 0 ? (double)(steps_per_sweep - 1) / nrest : 0.0;
+            for (int q = 0; q < 3; ++q) {
+                kms[HSVD_K_BLOCK_GRAM + q] += first[q] + rest[q] * scale;
+                ktimed[HSVD_K_BLOCK_GRAM + q] += 1 + nrest;
+            }
+        }
+        ++sweeps;
+        last.code = ctx->host_ctl->code;
+        last.maxt = ctx->host_ctl->maxt;
+        last.rank = ctx->host_ctl->rank != 0;
+        if (last.rank) break;
+        if ((last.code & 2) == 0) {
+            finished = true;
+            break;
+        }
+    }
+    // back to the input's column order for finalize: column rho[q] <- column q
+    HSVD_TRY(launch_wide_move(st, Gc, Gn, ldg, r, rc, true, nullptr, nullptr));
+    if (want_v) HSVD_TRY(launch_wide_move(st, Vc, Vn, ldg, r, rc, true, nullptr, nullptr));
+    out_G = Gn;
+    out_V = Vn;
+    out_rho = rc;
+    return last.rank ? HSVD_E_RANK : HSVD_OK;
+}
+
 // Newton-Schulz J-re-orthogonalisation of X (in w.V, FP64, promoted from the
 // FP32 sweeps), X <- X (3I - J X^T J X) / 2, followed by G <- G X.  The
 // products run on the library's FP64 MFMA kernels (X^T J X as a symmetric
@@ -604,9 +761,12 @@ hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int 
     if (prm.ordering != HSVD_ORD_MODMOD && prm.ordering != HSVD_ORD_ROUNDROBIN) return HSVD_E_INVAL;
     if (prm.precision != HSVD_FP64 && prm.precision != HSVD_MIXED) return HSVD_E_INVAL;
     if (prm.algo != HSVD_AUTO && prm.algo != HSVD_PAIRWISE && prm.algo != HSVD_BLOCK) return HSVD_E_INVAL;
-    if (prm.block != 0 && prm.block != block_width()) return HSVD_E_INVAL;
+    if (prm.block != 0 && prm.block != block_width() && prm.block != kWideB) return HSVD_E_INVAL;
     if (V && !prm.want_v) return HSVD_E_INVAL;
     const bool mixed = prm.precision == HSVD_MIXED;
+    // column blocks of 64: the wide block path, FP64 only
+    const bool wide = prm.block == kWideB;
+    if (wide && (mixed || prm.algo == HSVD_PAIRWISE)) return HSVD_E_INVAL;
     if (mixed && prm.algo == HSVD_PAIRWISE) return HSVD_E_INVAL;
     if (prm.inner_sweeps < 0 || prm.inner_sweeps > 100) return HSVD_E_INVAL;
     const bool full_block = prm.inner_sweeps > 0;
@@ -616,9 +776,9 @@ hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int 
     // the mixed path and the full-block method always run blocked.
     const hsvd_ctx::Tune &tn = ctx->tune[size_bucket(n)];
     const bool tuned = prm.algo == HSVD_AUTO && prm.block == 0 && !full_block && tn.valid;
-    const bool block = mixed || full_block || prm.algo == HSVD_BLOCK ||
+    const bool block = wide || mixed || full_block || prm.algo == HSVD_BLOCK ||
                        (prm.algo == HSVD_AUTO && (tuned ? tn.algo == HSVD_BLOCK : n >= 512));
-    const int b = block ? block_width() : 0;
+    const int b = block ? (wide ? kWideB : block_width()) : 0;
     const int mult = block ? 2 * b : 2;
     const int r = (n + mult - 1) / mult * mult;  // eq. (4.1) bordering
     if (r > kMaxOrder) return HSVD_E_INVAL;
@@ -645,6 +805,13 @@ hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int 
         if (want > 32) want = 32;  // the inner kernels sum at most 32 partial Grams
         rows_per_split = (chunks + want - 1) / want * 64;
         splits = (ldg + rows_per_split - 1) / rows_per_split;
+        if (wide) {
+            // equal row splits (a power of two dividing ldg / 16) for about 512
+            // (pair, split) products per step
+            splits = 1;
+            while (splits < 16 && pairs * splits < 512 && ldg % (32 * splits) == 0) splits *= 2;
+            rows_per_split = ldg / splits;
+        }
     }
     const int steps_per_sweep = block ? (prm.ordering == HSVD_ORD_MODMOD ? nb : nb - 1)
                                       : (prm.ordering == HSVD_ORD_MODMOD ? r : r - 1);
@@ -669,6 +836,7 @@ hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int 
         if (s != HSVD_OK) return s;
     }
     const Workspace w = carve(base, L);
+    Workspace fin = w;  // what finalize reads (the wide path returns its own buffers)
     hipStream_t st = ctx->stream;
     hipEvent_t *ev = timing ? ctx->events.data() : nullptr;
 
@@ -885,7 +1053,19 @@ hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int 
                 else if (ctx->host_ctl->rank) status = HSVD_E_RANK;
             }
         }
-        if (status == HSVD_OK) {
+        if (status == HSVD_OK && wide) {
+            double *fG = nullptr, *fV = nullptr;
+            int *frho = nullptr;
+            status = wide_sweeps(ctx, w, r, p, ldg, nb, splits, prm.ordering, want_v, prm.sort != 0, tol, tthresh,
+                                 prm.inner_sweeps, max_sweeps, timing, kms, klaunch, ktimed, sweeps, steps, last,
+                                 finished, fG, fV, frho);
+            code = last.code;
+            maxt_last = last.maxt;
+            if (status == HSVD_OK && !finished) status = HSVD_E_NOCONV;
+            fin.G = fG;
+            fin.V = fV;
+            fin.rho = frho;
+        } else if (status == HSVD_OK) {
             BlockArgs ba;
             ba.G = w.G;
             ba.V = want_v ? w.V : nullptr;  // the mixed path keeps V only when it is returned
@@ -921,7 +1101,7 @@ hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int 
         if (status == HSVD_E_DEVICE) return status;
     }
 
-    HSVD_TRY(launch_finalize(st, w, n, r, p, ldg, sigma, U, ldu, V, ldv, lambda, perm));
+    HSVD_TRY(launch_finalize(st, fin, n, r, p, ldg, sigma, U, ldu, V, ldv, lambda, perm));
     if (timing) HSVD_TRY(hipEventRecord(ev[1], st));
     HSVD_TRY(hipStreamSynchronize(st));
     if (info) {
@@ -977,9 +1157,11 @@ hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int 
                 const double vm = prec == 0 ? vmul : 2.0;
                 // with V carried by the block-oriented method, V's half of the
                 // update runs inside the inner launches and is counted there
-                const double vin = (vm > 1.0 && prm.inner_sweeps == 0) ? 1.0 : 0.0;
+                // (the wide path updates V in its update launch, and its Gram
+                // forms the whole (2b)^2 product)
+                const double vin = (vm > 1.0 && prm.inner_sweeps == 0 && !wide) ? 1.0 : 0.0;
                 info->kernel_bytes[kb] = visits * esz * b2 * rows;
-                info->kernel_flops[kb] = visits * 2.0 * (10.0 / 16.0) * b2 * b2 * rows;
+                info->kernel_flops[kb] = visits * 2.0 * (wide ? 1.0 : 10.0 / 16.0) * b2 * b2 * rows;
                 info->kernel_bytes[kb + 1] = vin * tcols * 2.0 * esz * rows;
                 info->kernel_flops[kb + 1] = vin * tcols * 2.0 * b2 * rows;
                 info->kernel_bytes[kb + 2] = tcols * 2.0 * esz * rows * (vm - vin);
@@ -1871,7 +2053,7 @@ hsvd_status hsvd_pivot_trace(hsvd_ctx *ctx, int ordering, int r, int steps, int 
 
 hsvd_status hsvd_block_trace(hsvd_ctx *ctx, int ordering, int r, int b, int steps, int *pairs)
 {
-    if (!ctx || b != block_width() || r < 2 * b || r % (2 * b) || r > kMaxOrder || steps < 0 ||
+    if (!ctx || (b != block_width() && b != kWideB) || r < 2 * b || r % (2 * b) || r > kMaxOrder || steps < 0 ||
         (steps > 0 && !pairs))
         return HSVD_E_INVAL;
     if (ordering != HSVD_ORD_MODMOD && ordering != HSVD_ORD_ROUNDROBIN) return HSVD_E_INVAL;

@@ -28,6 +28,11 @@
 // Batched use: blockIdx.z is the problem, the operands are offset by fixed
 // strides, p may come per problem, and a per-problem flag skips problems
 // that take no part in this product.
+//
+// Block-pair use (the b = 64 block path): the Gram G_P^T G_P of every block
+// pair, split over row ranges, and the in-place update G_P <- G_P W address
+// the two 64-column blocks of each pair in a position-ordered matrix through
+// a column map instead of a problem stride (GemmArgs).
 #include "internal.h"
 
 namespace hsvd {
@@ -57,7 +62,9 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g)
     __shared__ double As[2][kTM * kTK];
     __shared__ double Bs[2][kTN * kTK];
     const int z = blockIdx.z;
-    if (g.flag && ((g.flag[z] != 0) != (g.want != 0))) return;
+    // block-pair form: pair zg, K split ks (see GemmArgs)
+    const int zg = g.blk ? z / g.ksplit : z, ks = g.blk ? z % g.ksplit : 0;
+    if (g.flag && ((g.flag[zg] != 0) != (g.want != 0))) return;
     const int tiles_m = (g.M + kTM - 1) / kTM, tiles_n = (g.N + kTN - 1) / kTN;
     int tm, tn;
     if (SYM) {
@@ -78,10 +85,18 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g)
         tm = t / tiles_n;
         tn = t % tiles_n;
     }
-    const double *__restrict__ A = g.A + (size_t)z * g.sa;
-    const double *__restrict__ B = g.B + (size_t)z * g.sb;
-    double *__restrict__ C = g.C + (size_t)z * g.sc;
-    const int p = g.pvec ? g.pvec[z] : g.p;
+    // A and C may be the same matrix (in-place block-pair update): no
+    // restrict on them
+    const int mapA = g.map & 1, mapB = g.map & 2, mapC = g.map & 4;
+    const size_t koff = (size_t)ks * g.K;  // rows of this K split (transposed A, B)
+    const double *A = g.A + (mapA ? (TA ? koff : 0) : (size_t)z * g.sa);
+    const double *__restrict__ B = g.B + (mapB ? koff : (size_t)z * g.sb);
+    double *C = g.C + (mapC ? 0 : (size_t)z * g.sc);
+    const int2 bij = g.blk ? g.blk[zg] : make_int2(0, 0);
+    auto mcol = [&](int c) -> size_t {
+        return (size_t)(c < g.bw ? bij.x * g.bw + c : bij.y * g.bw + (c - g.bw));
+    };
+    const int p = g.pvec ? g.pvec[zg] : g.p;
     const int M = g.M, N = g.N, K = g.K;
     const int i0 = tm * kTM, j0 = tn * kTN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -96,14 +111,17 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g)
             if (!TA) {
                 // A(i, k) = A[k lda + i]: a wave reads 1 KB of one column
                 const int kk = u >> 6, ip = (u & 63) * 2, i = i0 + ip;
-                ra[q] = i < M ? *reinterpret_cast<const gd2 *>(A + (size_t)(k0 + kk) * g.lda + i) : gd2{0.0, 0.0};
+                const size_t ca = mapA ? mcol(k0 + kk) : (size_t)(k0 + kk);
+                ra[q] = i < M ? *reinterpret_cast<const gd2 *>(A + ca * g.lda + i) : gd2{0.0, 0.0};
             } else {
                 // A(i, k) = A[i lda + k]: 8 lanes read 128 bytes of one column
                 const int il = u >> 3, kp = (u & 7) * 2, i = i0 + il;
-                ra[q] = i < M ? *reinterpret_cast<const gd2 *>(A + (size_t)i * g.lda + k0 + kp) : gd2{0.0, 0.0};
+                ra[q] = i < M ? *reinterpret_cast<const gd2 *>(A + (mapA ? mcol(i) : (size_t)i) * g.lda + k0 + kp)
+                              : gd2{0.0, 0.0};
             }
             const int jl = u >> 3, kp = (u & 7) * 2, j = j0 + jl;
-            gd2 b = j < N ? *reinterpret_cast<const gd2 *>(B + (size_t)j * g.ldb + k0 + kp) : gd2{0.0, 0.0};
+            gd2 b = j < N ? *reinterpret_cast<const gd2 *>(B + (mapB ? mcol(j) : (size_t)j) * g.ldb + k0 + kp)
+                          : gd2{0.0, 0.0};
             if (SGN) {
                 if (k0 + kp >= p) b.x = -b.x;
                 if (k0 + kp + 1 >= p) b.y = -b.y;
@@ -171,7 +189,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g)
                 if (row >= M || col >= N) continue;
                 const double x = acc[m][n][v];
                 if (!SYM) {
-                    C[(size_t)col * g.ldc + row] = x;
+                    C[(mapC ? mcol(col) : (size_t)col) * g.ldc + row] = x;
                 } else if (row <= col) {
                     // both triangles from the entry with row <= col
                     C[(size_t)col * g.ldc + row] = x;
@@ -183,7 +201,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g)
 hipError_t launch_gemm(hipStream_t st, const GemmArgs &g, int nprob, bool trans_a, bool signed_b, bool symmetric)
 {
     if (g.M % 16 || g.N % 16 || g.K % kTK || g.M < 0 || g.N < 0 || g.K < 0 || nprob < 1) return hipErrorInvalidValue;
-    if (symmetric && (!trans_a || g.M != g.N)) return hipErrorInvalidValue;
+    if (symmetric && (!trans_a || g.M != g.N || (g.map & 4))) return hipErrorInvalidValue;
+    if (g.map && (!g.blk || g.bw < 1 || g.ksplit < 1 || nprob % g.ksplit)) return hipErrorInvalidValue;
     if (g.M == 0 || g.N == 0) return hipSuccess;
     const int tm = (g.M + kTM - 1) / kTM, tn = (g.N + kTN - 1) / kTN;
     const dim3 grid(symmetric ? tm * (tm + 1) / 2 : tm * tn, 1, nprob);

@@ -53,6 +53,12 @@ struct Workspace {
     // mixed path
     float *G32 = nullptr, *V32 = nullptr, *P32 = nullptr, *W32 = nullptr;
     double *T1 = nullptr, *T2 = nullptr;  // ldg x r FP64 scratch of the J-re-orthogonalisation
+    // wide block path (b = 64): second working copies (column moves after a
+    // sort), block pairs of the step, position payload of the sort, moved rho,
+    // per-pair rotation flags
+    double *G2 = nullptr, *V2 = nullptr;
+    int2 *blk = nullptr;
+    int *pl = nullptr, *rho2 = nullptr, *wact = nullptr;
 };
 
 struct Layout {
@@ -60,8 +66,8 @@ struct Layout {
     size_t bytes = 0;
     size_t off_G, off_V, off_d, off_rho, off_dtmp, off_rtmp, off_S, off_C, off_nrot, off_nskip,
         off_nact, off_ntc, off_maxt, off_ctl, off_P, off_W, off_active, off_S2, off_G32, off_V32, off_P32, off_W32,
-        off_T1, off_T2;
-    bool mixed = false;
+        off_T1, off_T2, off_G2, off_V2, off_blk, off_pl, off_rho2, off_wact;
+    bool mixed = false, wide = false;
 };
 
 // pairs/splits/b2 > 0 adds the block path buffers, mixed the FP32 copies and
@@ -479,6 +485,33 @@ size_t persist_slot_bytes();
 int persist_blocks_per_cu(int threads);
 hipError_t launch_batch_persist(hipStream_t st, const PersistArgs &pa, int threads, int workgroups);
 
+// The wide block path (wide_kernels.hip): column blocks of kWideB = 64, FP64,
+// working copies in position order.
+constexpr int kWideB = 64;
+struct WideArgs {
+    const double *partial = nullptr;  // pairs x splits x 128 x 128, column-major (both triangles)
+    int splits = 1;
+    double *W = nullptr;              // pairs x 128 x 128, column-major
+    const int2 *blk = nullptr;        // per pair: its blocks (I, J)
+    int p = 0;
+    double tol = 0.0, tthresh = 0.0;
+    int first = 0;                    // first outer step of a sweep (circle inner ordering)
+    int inner_sweeps = 0;             // full-block method: circle sweeps per outer step, at most
+    int *active = nullptr;            // per pair: 1 when a rotation was applied (W != I)
+    int *C = nullptr;
+    unsigned int *nrot = nullptr, *nskip = nullptr, *nact = nullptr, *ntc = nullptr;
+    double *maxt = nullptr;
+    Ctl *ctl = nullptr;
+};
+hipError_t launch_wide_blk(hipStream_t st, int ordering, int nb, int step, const int4 *S_in, int4 *S_out,
+                           int2 *blk);
+hipError_t launch_wide_inner(hipStream_t st, const WideArgs &a, int pairs);
+// gather: dst[:, q] = src[:, idx[q]] (and rho_out[q] = rho_in[idx[q]] when
+// rho_out is set); scatter: dst[:, idx[q]] = src[:, q]; q < r
+hipError_t launch_wide_move(hipStream_t st, const double *src, double *dst, int ldg, int r, const int *idx,
+                            bool scatter, const int *rho_in, int *rho_out);
+hipError_t launch_wide_iota(hipStream_t st, int *v, int r);
+
 // mixed path helpers
 hipError_t launch_to_fp32(hipStream_t st, const double *G, float *G32, float *V32, int ldg, int r);
 hipError_t launch_promote(hipStream_t st, const float *X32, double *X, int ldg, int r);
@@ -493,11 +526,24 @@ hipError_t launch_synth(hipStream_t st, double *G, int n, unsigned long long see
 // of 16, leading dimensions and strides even.  Batched (nprob > 1): problem
 // z = blockIdx.z at offsets z * (sa, sb, sc), p = pvec[z] when pvec is set,
 // and with flag set only the problems with (flag[z] != 0) == want run.
+//
+// Block-pair form (the wide block path): with `blk` set, problem z belongs to
+// block pair g = z / ksplit and to K split s = z % ksplit.  The operands named
+// in `map` (1 = A, 2 = B, 4 = C) are not offset by z but address the columns
+// of a position-ordered matrix through the pair's two blocks of bw columns:
+// column c is column blk[g].x * bw + c for c < bw, blk[g].y * bw + c - bw
+// otherwise (for A: its M index when transposed, its K index otherwise; for B
+// and C: their N index).  A K split s reads rows [s K, (s + 1) K) of the
+// transposed A and of B.  flag and pvec are then indexed by g.  In-place
+// products (A and C the same matrix, N = its mapped width) are allowed: a
+// workgroup reads all of its rows before it writes them.
 struct GemmArgs {
     const double *A = nullptr, *B = nullptr;
     double *C = nullptr;
     int M = 0, N = 0, K = 0;
     int lda = 0, ldb = 0, ldc = 0;
+    const int2 *blk = nullptr;
+    int bw = 0, map = 0, ksplit = 1;
     long long sa = 0, sb = 0, sc = 0;
     int p = 0;
     const int *pvec = nullptr;

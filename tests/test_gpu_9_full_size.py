@@ -119,3 +119,31 @@ def test_full_size_vs_oracle(hsvd_ctx, name, precision):
         assert i["fp64_restart"] == 0
         assert i["reorth_resid"] <= 16384 * n * 2.0 ** -53
     check_invariants_gpu(Gt, p, R, tol=1e-15 * n, sweeps=i["sweeps"] + i["sweeps_fp32"])
+
+
+@pytest.mark.timeout(900)
+def test_full_size_wide_vs_oracle(hsvd_ctx):
+    """The wide block path (b = 64) on colscaled n = 4096 against the oracle's
+    stored b = 32 result: another block width is another trajectory, so sigma
+    is held to 10x the oracle's ordering spread, like the mixed path."""
+    import torch
+
+    from paper_1008_1371_amd import hsvd as H
+    name = "colscaled4096"
+    fx = _fixture(name)
+    G, p = W.workload(name)
+    n = G.shape[0]
+    Gt = torch.from_numpy(G).cuda()
+    R = H.hsvd_solve(hsvd_ctx, Gt, p, H.hsvd_default_params(algo=H.BLOCK, block=64), check=False)
+    i = R["info"]
+    say(name, "b = 64 status", R["status"], "sweeps", i["sweeps"], "oracle (b = 32) sweeps", fx["meta"]["sweeps"],
+        "ms", i["ms_total"])
+    assert R["status"] == 0 and i["block"] == 64
+    e = _vs_fixture(fx, R, p)
+    sp = _oracle_spread(fx)
+    say("   vs oracle", e)
+    assert e["sigma_norm"] <= max(1e-12, 10 * fx["meta"]["ordering_spread"]["sigma_norm"]), e
+    assert e["sigma_max"] <= max(1e-12, 10 * sp["sigma_max"]), (e, sp)
+    gate = max(1e-12, 10 * max(sp["U"], sp["V"]))
+    assert e["U"] <= gate and e["V"] <= gate, (e, sp)
+    check_invariants_gpu(Gt, p, R, tol=1e-15 * n, sweeps=i["sweeps"])
