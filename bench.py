@@ -85,6 +85,9 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--batched", type=int, default=10000,
                     help="also time the batched solver on this many small problems (0: skip)")
+    ap.add_argument("--block", type=int, default=0, choices=[0, 32, 64],
+                    help="block width of the FP64 block path (0: the library's default, 32); 64 runs the wide "
+                         "block path, FP64 only")
     ap.add_argument("--inner-sweeps", type=int, default=0,
                     help="block modes: 0 = block-oriented method; k > 0 = full-block method with at most "
                          "k inner sweeps per pivot block")
@@ -401,19 +404,28 @@ def main():
 
     def variant(mode):
         # the counter measurements hold for the default variant of a mode only
-        return mode + ("/full-block" if args.inner_sweeps > 0 else "") + ("/no-v" if args.no_v else "")
+        return (mode + ("/full-block" if args.inner_sweeps > 0 else "") + ("/no-v" if args.no_v else "") +
+                ("/b64" if args.block == 64 else ""))
 
     def params(mode):
         prm = H.hsvd_default_params(algo=H.PAIRWISE if mode == "pairwise" else H.BLOCK,
                                     precision=H.MIXED if mode == "mixed" else H.FP64,
                                     want_v=0 if args.no_v else 1,
-                                    inner_sweeps=0 if mode == "pairwise" else args.inner_sweeps)
+                                    inner_sweeps=0 if mode == "pairwise" else args.inner_sweeps,
+                                    block=args.block if mode == "fp64" else 0)
         if args.max_sweeps > 0:
             prm.max_sweeps = args.max_sweeps
         return prm
 
     runs = {}
     modes = ["fp64", "mixed"] if args.mode == "both" else [args.mode]
+    names = list(H.KERNEL_NAMES)
+    if args.block == 64:
+        # b = 64 is an FP64 path; its kernel classes are the block-pair GEMMs
+        # and the wide inner kernel
+        modes = ["fp64"]
+        names[1:4] = ["gemm_f64_kernel (block-pair Gram, b = 64)", "wide_inner_kernel",
+                      "gemm_f64_kernel (block-pair update, b = 64)"]
     results = {}
     for mode in modes:
         ms, infos, R = timed(H, ctx, G, p, params(mode), out, args.steps, args.warmup, check)
@@ -446,7 +458,7 @@ def main():
                    "tol": 1e-15 * n, "sweeps_fp32": last["sweeps_fp32"], "sweeps_fp64": last["sweeps"],
                    "reorth_iters": last["reorth_iters"], "rotations": last["rotations"],
                    "steps_per_solve": last["steps"]},
-        "roofline": roofline(infos, H.KERNEL_NAMES, peaks, args.workload, variant(head)),
+        "roofline": roofline(infos, names, peaks, args.workload, variant(head)),
     }
     if acc is not None:
         line["accuracy"] = acc
@@ -454,7 +466,7 @@ def main():
         if mode == head:
             continue
         line[mode] = {"value": 1000.0 / m_ms, "ms_per_step": m_ms, "sweeps": m_infos[-1]["sweeps"],
-                      "roofline": roofline(m_infos, H.KERNEL_NAMES, peaks, args.workload, variant(mode)),
+                      "roofline": roofline(m_infos, names, peaks, args.workload, variant(mode)),
                       "accuracy": m_acc}
         line["speedup_vs_" + mode] = m_ms / ms
     if "fp64" in results and "mixed" in results:

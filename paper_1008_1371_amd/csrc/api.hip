@@ -434,7 +434,7 @@ hsvd_status block_sweeps(hsvd_ctx *ctx, const Workspace &w, BlockArgsT<T> &ba, c
     int cus = 0;
     if (fuse && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
         return HSVD_E_DEVICE;
-    ba.vrows = fuse ? v_update_role_rows(pairs, ldg, cus) : 0;
+    ba.vrows = fuse ? v_update_role_rows(pairs, ldg, cus, sizeof(T) == 8) : 0;
     const int vwgs = fuse ? v_update_role_wgs(pairs, ldg, ba.vrows) : 0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         for (int k = 0; k < steps_per_sweep; ++k, ++gstep) {

@@ -379,7 +379,7 @@ template <typename T>
 hipError_t launch_block_update(hipStream_t st, const BlockArgsT<T> &a, int which = UPD_BOTH);
 // Rows per workgroup and workgroups that the V update of one outer step takes
 // inside an inner launch (cus: compute units of the device).
-int v_update_role_rows(int pairs, int ldg, int cus);
+int v_update_role_rows(int pairs, int ldg, int cus, bool fp64);
 int v_update_role_wgs(int pairs, int ldg, int vrows);
 template <typename T>
 hipError_t launch_colnorm_pos(hipStream_t st, const T *G, int ldg, const int *rho, double *d, int r);
