@@ -88,6 +88,9 @@ def parse():
     ap.add_argument("--block", type=int, default=0, choices=[0, 32, 64],
                     help="block width of the FP64 block path (0: the library's default, 32); 64 runs the wide "
                          "block path, FP64 only")
+    ap.add_argument("--persistent", type=int, default=0, choices=[0, 1, 2],
+                    help="pairwise path: 0 one launch per step (graph replay), 1 one persistent launch with "
+                         "per-column readiness between steps, 2 the same with a grid barrier per step")
     ap.add_argument("--inner-sweeps", type=int, default=0,
                     help="block modes: 0 = block-oriented method; k > 0 = full-block method with at most "
                          "k inner sweeps per pivot block")
@@ -405,14 +408,16 @@ def main():
     def variant(mode):
         # the counter measurements hold for the default variant of a mode only
         return (mode + ("/full-block" if args.inner_sweeps > 0 else "") + ("/no-v" if args.no_v else "") +
-                ("/b64" if args.block == 64 else ""))
+                ("/b64" if args.block == 64 else "") +
+                (f"/persistent{args.persistent}" if mode == "pairwise" and args.persistent else ""))
 
     def params(mode):
         prm = H.hsvd_default_params(algo=H.PAIRWISE if mode == "pairwise" else H.BLOCK,
                                     precision=H.MIXED if mode == "mixed" else H.FP64,
                                     want_v=0 if args.no_v else 1,
                                     inner_sweeps=0 if mode == "pairwise" else args.inner_sweeps,
-                                    block=args.block if mode == "fp64" else 0)
+                                    block=args.block if mode == "fp64" else 0,
+                                    persistent=args.persistent if mode == "pairwise" else 0)
         if args.max_sweeps > 0:
             prm.max_sweeps = args.max_sweeps
         return prm
@@ -426,6 +431,8 @@ def main():
         modes = ["fp64"]
         names[1:4] = ["gemm_f64_kernel (block-pair Gram, b = 64)", "wide_inner_kernel",
                       "gemm_f64_kernel (block-pair update, b = 64)"]
+    if args.mode == "pairwise" and args.persistent:
+        names[0] = "pair_persist_kernel (all sweeps, one launch)"
     results = {}
     for mode in modes:
         ms, infos, R = timed(H, ctx, G, p, params(mode), out, args.steps, args.warmup, check)

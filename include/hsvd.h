@@ -88,6 +88,15 @@ typedef struct {
                         precision, in launches grouped by bordered order);
                         1 = grouped launches for every problem.  The two give
                         bit-identical results                                      */
+    int persistent;  /* pairwise path: 0 = one launch per parallel step (replayed from a
+                        HIP graph when graph = 1) and the stop rule checked on the host
+                        after every sweep; 1 = all sweeps in one persistent cooperative
+                        launch: a pair waits only for the two visits of the previous
+                        step that last held its columns (per-column visit counts), and
+                        the diagonal sort and the stop rule (eq. 4.2) run on the device
+                        at every sweep's end; 2 = the same launch with a grid barrier
+                        between steps.  All three give bit-identical results; the
+                        block path ignores it.  Other values: HSVD_E_INVAL          */
 } hsvd_params;
 
 /* Kernel classes timed in hsvd_info (index into the kernel_* arrays). */

@@ -25,6 +25,7 @@ struct hsvd_ctx {
     void *aux = nullptr;                     // buffers of a solve with jsig in any order, autotuner input
     size_t aux_bytes = 0;
     hsvd::Ctl *host_ctl = nullptr;           // pinned
+    hsvd::PersistCtl *host_pctl = nullptr;   // pinned, in the same allocation
     std::vector<hipEvent_t> events;          // reusable timing events
     hipStream_t cap = nullptr;               // non-blocking stream for graph capture (default priority)
     hipEvent_t join = nullptr;               // orders the capture stream with the caller's stream
@@ -164,6 +165,8 @@ Layout make_layout(int n, int r, int ldg, bool want_v, int pairs, int splits, in
     L.off_ntc = take(sizeof(unsigned int) * slots);
     L.off_maxt = take(sizeof(double) * slots);
     L.off_ctl = take(sizeof(Ctl));
+    L.off_ver = take(sizeof(unsigned int) * r);
+    L.off_pctl = take(sizeof(PersistCtl));
     const size_t bb = (size_t)b2 * b2;
     L.off_P = take(sizeof(double) * (size_t)pairs * splits * bb);
     // W and the touched-column masks are double-buffered by step parity: the
@@ -209,6 +212,8 @@ Workspace carve(void *base, const Layout &L)
     w.ntc = reinterpret_cast<unsigned int *>(b + L.off_ntc);
     w.maxt = reinterpret_cast<double *>(b + L.off_maxt);
     w.ctl = reinterpret_cast<Ctl *>(b + L.off_ctl);
+    w.ver = reinterpret_cast<unsigned int *>(b + L.off_ver);
+    w.pctl = reinterpret_cast<PersistCtl *>(b + L.off_pctl);
     if (L.pairs > 0) {
         w.P = reinterpret_cast<double *>(b + L.off_P);
         w.W = reinterpret_cast<double *>(b + L.off_W);
@@ -290,6 +295,7 @@ void hsvd_default_params(hsvd_params *prm)
     prm->inner_sweeps = 0;
     prm->reorth_accept = 0.0;
     prm->batch_mode = 0;
+    prm->persistent = 0;
 }
 
 hsvd_status hsvd_init(hsvd_ctx **out, int device, void *hip_stream)
@@ -305,11 +311,13 @@ hsvd_status hsvd_init(hsvd_ctx **out, int device, void *hip_stream)
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     void *h = nullptr;
-    if (hipHostMalloc(&h, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+    const size_t pctl_at = align_up(sizeof(Ctl), 64);
+    if (hipHostMalloc(&h, pctl_at + sizeof(PersistCtl), hipHostMallocDefault) != hipSuccess) {
         delete ctx;
         return HSVD_E_DEVICE;
     }
     ctx->host_ctl = static_cast<Ctl *>(h);
+    ctx->host_pctl = reinterpret_cast<PersistCtl *>(static_cast<char *>(h) + pctl_at);
     if (!scratch_address(device)) {
         hipHostFree(h);
         delete ctx;
@@ -769,6 +777,7 @@ hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int 
     if (wide && (mixed || prm.algo == HSVD_PAIRWISE)) return HSVD_E_INVAL;
     if (mixed && prm.algo == HSVD_PAIRWISE) return HSVD_E_INVAL;
     if (prm.inner_sweeps < 0 || prm.inner_sweeps > 100) return HSVD_E_INVAL;
+    if (prm.persistent < 0 || prm.persistent > 2) return HSVD_E_INVAL;
     const bool full_block = prm.inner_sweeps > 0;
     if (full_block && prm.algo == HSVD_PAIRWISE) return HSVD_E_INVAL;
     // The block path needs at least two blocks of b columns; AUTO takes the
@@ -895,9 +904,55 @@ hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int 
         // per-launch gap of stream launches is a large share of it.  The
         // sweep runs on the context's capture stream, joined to the caller's
         // stream before and after.
+        if (prm.persistent) {
+            // every sweep in one persistent launch; the device sorts, reduces
+            // and applies the stop rule after each sweep
+            PairPersistArgs pa;
+            pa.a = a;
+            pa.a.step = 0;
+            pa.steps = steps_per_sweep;
+            pa.max_sweeps = max_sweeps;
+            pa.sort = prm.sort ? 1 : 0;
+            pa.dataflow = prm.persistent == 1 ? 1 : 0;
+            pa.dtmp = w.dtmp;
+            pa.rtmp = w.rtmp;
+            pa.nact = w.nact;
+            pa.ntc = w.ntc;
+            pa.ver = w.ver;
+            pa.pc = w.pctl;
+            int clock_khz = 0;
+            HSVD_TRY(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, ctx->device));
+            // one wait of a healthy launch lasts at most a step or a sweep's
+            // end; 2 s of wall clock means the launch cannot go on
+            pa.spin_limit = 2000LL * (clock_khz > 0 ? clock_khz : 100000);
+            int grid = 0;
+            if (timing) HSVD_TRY(hipEventRecord(ev[2], st));
+            const hipError_t le = launch_pair_persist(st, pa, &grid);
+            if (le == hipErrorNotSupported || le == hipErrorCooperativeLaunchTooLarge) return HSVD_E_INVAL;
+            if (le != hipSuccess) return HSVD_E_DEVICE;
+            if (timing) HSVD_TRY(hipEventRecord(ev[3], st));
+            HSVD_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+            HSVD_TRY(hipMemcpyAsync(ctx->host_pctl, w.pctl, sizeof(PersistCtl), hipMemcpyDeviceToHost, st));
+            HSVD_TRY(hipStreamSynchronize(st));
+            if (ctx->host_pctl->err) return HSVD_E_DEVICE;
+            sweeps = ctx->host_pctl->sweeps;
+            steps = (long long)sweeps * steps_per_sweep;
+            klaunch[HSVD_K_PAIR_STEP] += 1;
+            ktimed[HSVD_K_PAIR_STEP] += 1;
+            if (timing) {
+                float ms = 0.f;
+                HSVD_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
+                kms[HSVD_K_PAIR_STEP] += ms;
+            }
+            code = ctx->host_ctl->code;
+            maxt_last = ctx->host_ctl->maxt;
+            if (ctx->host_pctl->stop == 2) status = HSVD_E_RANK;
+            else if (ctx->host_pctl->stop == 1) converged = true;
+            if (status == HSVD_OK && !converged) status = HSVD_E_NOCONV;
+        }
         SweepGraph sg(ctx, st);
         hipStream_t q = st;
-        const bool graph = prm.graph && mode.graphs;
+        const bool graph = prm.graph && mode.graphs && !prm.persistent;
         if (graph) {
             HSVD_TRY(sg.begin(q));
             for (int k = 0; k < steps_per_sweep; ++k) {
@@ -910,7 +965,7 @@ hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int 
             }
             HSVD_TRY(sg.end(q));
         }
-        for (int sw = 0; sw < max_sweeps; ++sw) {
+        for (int sw = 0; sw < (prm.persistent ? 0 : max_sweeps); ++sw) {
             if (timing) HSVD_TRY(hipEventRecord(ev[2], q));
             if (graph) {
                 HSVD_TRY(hipGraphLaunch(sg.exec, q));
@@ -945,7 +1000,7 @@ hsvd_status solve_canonical(hsvd_ctx *ctx, const double *G, int lda, int n, int 
                 break;
             }
         }
-        if (status == HSVD_OK && !converged) status = HSVD_E_NOCONV;
+        if (!prm.persistent && status == HSVD_OK && !converged) status = HSVD_E_NOCONV;
     } else if (status == HSVD_OK) {
         SweepResult last = {0, 0.0, false};
         bool finished = false;

@@ -30,6 +30,17 @@ struct Ctl {
     double nsres;              // Newton-Schulz residual max |J X^T J X - I| (mixed path)
 };
 
+// Control block of the persistent pairwise kernel (device memory, zeroed
+// before its launch).
+struct PersistCtl {
+    unsigned int count;  // grid barrier: arrivals at the current barrier
+    unsigned int gen;    // grid barrier: completed barriers
+    int err;             // a wait passed its time limit: every workgroup leaves
+    int stop;            // set at a sweep's end: 1 converged (eq. 4.2), 2 rank deficient
+    int sweeps;          // sweeps completed
+    int pad[3];
+};
+
 struct Workspace {
     double *G = nullptr;      // ldg x r, working copy of G (bordered, zero-padded rows)
     double *V = nullptr;      // ldg x r, accumulated V^{-T}
@@ -45,6 +56,8 @@ struct Workspace {
     unsigned int *ntc = nullptr;    // r/2: per-slot columns touched by rotations, summed over steps (block path)
     double *maxt = nullptr;         // r/2: per-slot largest |t| of the current sweep
     Ctl *ctl = nullptr;
+    unsigned int *ver = nullptr;  // r: completed visits per position (persistent pairwise kernel)
+    PersistCtl *pctl = nullptr;
     // block path
     double *P = nullptr;      // pairs x splits x (2b)^2 partial Gram matrices
     double *W = nullptr;      // pairs x (2b)^2 accumulated inner transformations
@@ -65,7 +78,7 @@ struct Layout {
     int n = 0, r = 0, ldg = 0, pairs = 0, splits = 0, b2 = 0;
     size_t bytes = 0;
     size_t off_G, off_V, off_d, off_rho, off_dtmp, off_rtmp, off_S, off_C, off_nrot, off_nskip,
-        off_nact, off_ntc, off_maxt, off_ctl, off_P, off_W, off_active, off_S2, off_G32, off_V32, off_P32, off_W32,
+        off_nact, off_ntc, off_maxt, off_ctl, off_ver, off_pctl, off_P, off_W, off_active, off_S2, off_G32, off_V32, off_P32, off_W32,
         off_T1, off_T2, off_G2, off_V2, off_blk, off_pl, off_rho2, off_wact;
     bool mixed = false, wide = false;
 };
@@ -325,6 +338,25 @@ struct StepArgs {
     double tol, tthresh;
 };
 
+// The persistent pairwise kernel: every sweep of a solve in one cooperative
+// launch.  Steps are separated either by a grid barrier or, per column, by
+// the completed-visit counts in ver (a pair waits only for the two pairs that
+// last held its columns); at a sweep's end a grid barrier, the sort and the
+// convergence test (eq. 4.2) run on the device.
+struct PairPersistArgs {
+    StepArgs a;
+    int steps;        // steps per sweep
+    int max_sweeps;
+    int sort;         // sort the diagonal after every sweep
+    int dataflow;     // 1: per-column readiness between steps; 0: a grid barrier
+    double *dtmp;     // r: sort scratch
+    int *rtmp;        // 2r: sort scratch (moved rho, then ranks)
+    unsigned int *nact, *ntc;  // per-slot counters the reduction resets
+    unsigned int *ver;
+    PersistCtl *pc;
+    long long spin_limit;  // wall-clock ticks one wait may take before the launch gives up
+};
+
 template <typename T>
 struct BlockArgsT {
     T *G;
@@ -392,6 +424,9 @@ hipError_t launch_precompute(hipStream_t st, const Workspace &w, int r, int ldg)
 hipError_t launch_pair_step(hipStream_t st, const StepArgs &a);
 hipError_t launch_sort(hipStream_t st, double *d, int *rho, double *dtmp, int *rtmp, int r, int p);
 hipError_t launch_sweep_reduce(hipStream_t st, const Workspace &w, int slots);
+// Cooperative launch of the persistent pairwise kernel; *grid receives the
+// workgroup count (at most one per slot, at most what the device holds at once).
+hipError_t launch_pair_persist(hipStream_t st, const PairPersistArgs &a, int *grid);
 hipError_t launch_finalize(hipStream_t st, const Workspace &w, int n, int r, int p, int ldg,
                            double *sigma, double *U, int ldu, double *V, int ldv, double *lambda,
                            int *perm);

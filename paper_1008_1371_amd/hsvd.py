@@ -34,7 +34,7 @@ class hsvd_params(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int), ("tol", ctypes.c_double),
                 ("t_thresh", ctypes.c_double), ("graph", ctypes.c_int),
                 ("inner_sweeps", ctypes.c_int), ("reorth_accept", ctypes.c_double),
-                ("batch_mode", ctypes.c_int)]
+                ("batch_mode", ctypes.c_int), ("persistent", ctypes.c_int)]
 
 
 NKERNELS = 8
