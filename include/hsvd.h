@@ -83,11 +83,14 @@ typedef struct {
     double reorth_accept; /* mixed path: largest accepted max |J X^T J X - I| after the
                         Newton-Schulz J-re-orthogonalisation of V (above it the
                         solve restarts from G in FP64); <= 0: 16384 n u, u = 2^-53  */
-    int batch_mode;  /* hsvd_solve_batched: 0 = every FP64 block-oriented problem with
-                        n <= 256 in one persistent launch (the others, and mixed
-                        precision, in launches grouped by bordered order);
-                        1 = grouped launches for every problem.  The two give
-                        bit-identical results                                      */
+    int batch_mode;  /* hsvd_solve_batched: 0 = every block-oriented problem with
+                        n <= 256, FP64 or mixed, in one persistent launch (the
+                        others, and the full-block method, in launches grouped by
+                        bordered order); 1 = grouped launches for every problem.
+                        FP64: the two give bit-identical results.  Mixed: each
+                        gives a valid mixed trajectory (the FP64 sweeps of a
+                        problem start at the stepper phase its own FP32 sweeps
+                        left, in the grouped launches at the group's)          */
     int persistent;  /* pairwise path: 0 = one launch per parallel step (replayed from a
                         HIP graph when graph = 1) and the stop rule checked on the host
                         after every sweep; 1 = all sweeps in one persistent cooperative
@@ -226,18 +229,20 @@ hsvd_status hsvd_solve_noalloc(hsvd_ctx *ctx, const double *G, int lda, int n, i
  *                    ldg, reorth_iters, reorth_resid, fp64_restart, rotations,
  *                    skips, active_pairs; ms_total is the device time of the
  *                    whole batched call; the kernel_* arrays are zero.
- * FP64 problems of the block-oriented method with n <= 256 run in one
- * persistent launch (prm->batch_mode = 0, the default; captured as a HIP graph
- * when prm->graph is set): each workgroup takes problems from a device work
- * queue, largest n first, and solves each one completely -- Gram, inner
- * rotations and update of every block pair, sort and the stop rule of
- * eq. (4.2) per sweep, output extraction -- with no host round trip.  The
- * other problems (n > 256, mixed precision, the full-block method, or
+ * Problems of the block-oriented method with n <= 256 run in one persistent
+ * launch (prm->batch_mode = 0, the default; captured as a HIP graph when
+ * prm->graph is set): each workgroup takes problems from a device work queue,
+ * largest n first, and solves each one completely -- Gram, inner rotations
+ * and update of every block pair, sort and the stop rule of eq. (4.2) per
+ * sweep; with mixed precision first the FP32 sweeps, the switch rule and the
+ * J-re-orthogonalisation of V -- then output extraction, with no host round
+ * trip.  The other problems (n > 256, the full-block method, or
  * batch_mode = 1) are grouped by their bordered order (a multiple of 2b); each
  * group runs as one sequence of launches that covers all of its problems,
- * with the stop rule decided per problem on the device.  Both forms give
- * bit-identical results.  Returns HSVD_OK when every problem converged, else
- * the status of the first problem that did not.  Synchronises. */
+ * with the stop rule decided per problem on the device.  In FP64 both forms
+ * give bit-identical results (in mixed precision see batch_mode).  Returns
+ * HSVD_OK when every problem converged, else the status of the first problem
+ * that did not.  Synchronises. */
 hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n, const int *p, const long long *off,
                                const long long *voff, const double *G, const hsvd_params *prm, double *sigma,
                                double *U, double *V, double *lambda, hsvd_info *info);
@@ -256,8 +261,8 @@ hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n, const int
  * Errors: HSVD_E_INVAL (n < 2 or n > 16382).  Synchronises. */
 hsvd_status hsvd_autotune(hsvd_ctx *ctx, int n, int *best_algo, int *best_wg);
 
-/* Autotuner of the batched solver.  FP64 block-oriented problems with n <= 256
- * run in one persistent launch in which each workgroup solves whole problems;
+/* Autotuner of the batched solver.  Block-oriented problems with n <= 256 run
+ * in one persistent launch in which each workgroup solves whole problems;
  * its width (256, 512 or 1024 threads per problem: the inner rotations and the
  * column updates of a block pair spread over all of them) is a speed-only
  * choice.  This call times the three widths on a sample of at most 4096 of the

@@ -1633,6 +1633,8 @@ static hsvd_status batch_persistent(hsvd_ctx *ctx, hipStream_t st, const std::ve
     const size_t o_rot = take_bytes(o, sizeof(unsigned long long) * batch);
     const size_t o_skip = take_bytes(o, sizeof(unsigned long long) * batch);
     const size_t o_act = take_bytes(o, sizeof(unsigned long long) * batch);
+    const size_t o_s32 = take_bytes(o, sizeof(int) * batch), o_ni = take_bytes(o, sizeof(int) * batch);
+    const size_t o_rs = take_bytes(o, sizeof(int) * batch), o_nr = take_bytes(o, sizeof(double) * batch);
     const size_t o_slots = take_bytes(o, persist_slot_bytes() * (size_t)wgs);
     hsvd_status s = ensure_ws(ctx, o);
     if (s != HSVD_OK) return s;
@@ -1668,6 +1670,12 @@ static hsvd_status batch_persistent(hsvd_ctx *ctx, hipStream_t st, const std::ve
     pa.rot = reinterpret_cast<unsigned long long *>(base + o_rot);
     pa.skip = reinterpret_cast<unsigned long long *>(base + o_skip);
     pa.act = reinterpret_cast<unsigned long long *>(base + o_act);
+    pa.mixed = prm.precision == HSVD_MIXED ? 1 : 0;
+    pa.reorth_accept = prm.reorth_accept;
+    pa.sweeps32 = reinterpret_cast<int *>(base + o_s32);
+    pa.nsiters = reinterpret_cast<int *>(base + o_ni);
+    pa.restart = reinterpret_cast<int *>(base + o_rs);
+    pa.nsres = reinterpret_cast<double *>(base + o_nr);
     pa.slots = base + o_slots;
     if (prm.graph) {
         if (!ctx->cap) HSVD_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
@@ -1708,6 +1716,14 @@ static hsvd_status batch_persistent(hsvd_ctx *ctx, hipStream_t st, const std::ve
     HSVD_TRY(hipMemcpyAsync(hr.data(), pa.rot, sizeof(unsigned long long) * batch, hipMemcpyDeviceToHost, st));
     HSVD_TRY(hipMemcpyAsync(hk.data(), pa.skip, sizeof(unsigned long long) * batch, hipMemcpyDeviceToHost, st));
     HSVD_TRY(hipMemcpyAsync(ha.data(), pa.act, sizeof(unsigned long long) * batch, hipMemcpyDeviceToHost, st));
+    std::vector<int> h32(batch), hni(batch), hrs(batch);
+    std::vector<double> hres(batch);
+    if (pa.mixed) {
+        HSVD_TRY(hipMemcpyAsync(h32.data(), pa.sweeps32, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+        HSVD_TRY(hipMemcpyAsync(hni.data(), pa.nsiters, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+        HSVD_TRY(hipMemcpyAsync(hrs.data(), pa.restart, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+        HSVD_TRY(hipMemcpyAsync(hres.data(), pa.nsres, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+    }
     HSVD_TRY(hipStreamSynchronize(st));
     const int b = block_width();
     for (int k : ids) {
@@ -1724,6 +1740,12 @@ static hsvd_status batch_persistent(hsvd_ctx *ctx, hipStream_t st, const std::ve
         pi.skips = (long long)hk[k];
         pi.steps = (long long)hsw[k] * (prm.ordering == HSVD_ORD_MODMOD ? nb : nb - 1);
         pi.active_pairs = (long long)ha[k];
+        if (pa.mixed) {
+            pi.sweeps_fp32 = h32[k];
+            pi.reorth_iters = hni[k];
+            pi.fp64_restart = hrs[k];
+            pi.reorth_resid = hres[k] <= 1.0 ? hres[k] : 0.0;
+        }
     }
     return HSVD_OK;
 }
@@ -1773,7 +1795,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
     // rounded up to 2b, one sequence of launches per group
     std::vector<int> pers;
     std::vector<std::vector<int>> groups(1024 / (2 * b) + 1);
-    const bool persist_ok = !mixed && prm.inner_sweeps == 0 && prm.batch_mode == 0;
+    const bool persist_ok = prm.inner_sweeps == 0 && prm.batch_mode == 0;
     for (int k = 0; k < batch; ++k) {
         if (persist_ok && n[k] <= kPersistMaxOrder)
             pers.push_back(k);

@@ -22,9 +22,17 @@
 // set-up, norm, sort and stop-rule steps repeat its arithmetic in the same
 // order: for the same problems the results are bit-identical to it.
 //
+// Mixed precision runs the whole mixed solve of a problem in its workgroup
+// too: FP32 block sweeps on FP32 copies (the same building blocks with
+// T = float) until the problem's own switch rule, the Newton-Schulz
+// J-re-orthogonalisation of V on FP64 MFMA inside the workgroup, G1 = G X,
+// then the FP64 sweeps (or, after a rank flag in FP32 or a residual above
+// the accepted bound, the FP64 sweeps from G).
+//
 // Each workgroup works in a slot of device memory of its own (working copies
 // of G and V, partial Grams, W, the kept diagonal, rho, stepper state and
-// counters), sized for the largest order the kernel takes (n <= 256).
+// counters; FP32 copies and FP64 product scratch for mixed precision), sized
+// for the largest order the kernel takes (n <= 256).
 #include "block_device.h"
 
 namespace hsvd {
@@ -43,6 +51,7 @@ constexpr int kPUpdLd = kB2 + 8;                // LDS row stride of W in the up
 union PersistLds {
     CircleLds circle;
     CrossLds<double> cross;
+    CrossLds<float> cross32;
     double red[kGramRed];
     struct {
         double Wl[kB2 * kPUpdLd];
@@ -66,7 +75,12 @@ __shared__ PersistLds g_lds;
 // raw storage: the argument struct has default member initialisers
 __shared__ __align__(16) unsigned char g_args[sizeof(BlockArgsT<double>)];
 
+__shared__ __align__(16) unsigned char g_args32[sizeof(BlockArgsT<float>)];
+__shared__ __align__(16) unsigned char g_gemm[sizeof(GemmArgs)];
+
 __device__ __forceinline__ BlockArgsT<double> &pargs() { return *reinterpret_cast<BlockArgsT<double> *>(g_args); }
+__device__ __forceinline__ BlockArgsT<float> &pargs32() { return *reinterpret_cast<BlockArgsT<float> *>(g_args32); }
+__device__ __forceinline__ GemmArgs &pgemm() { return *reinterpret_cast<GemmArgs *>(g_gemm); }
 
 // NT threads per workgroup (256, 512 or 1024): the inner solves and the
 // update spread over all of them, the Gram runs on the first 256.
@@ -90,9 +104,83 @@ __device__ __noinline__ void phase_update(int q, int M, unsigned long long mask)
                                                g_lds.upd.cols, g_lds.upd.tl);
 }
 
+// The FP32 phases of a mixed solve: the same building blocks on the FP32
+// working copies (the rotations still computed in FP64); the FP32 update
+// re-reads W from LDS at the FP32 row stride of the per-launch update.
+constexpr int kPUpdLd32 = kB2 + 16;
+__device__ __noinline__ void phase_gram32(int q)
+{
+    gram_pair<float>(pargs32(), q, 0, reinterpret_cast<float *>(g_lds.red));
+}
+template <int NT>
+__device__ __noinline__ void phase_circle32(int q)
+{
+    inner_circle_pair<float, NT>(pargs32(), q, g_lds.circle);
+}
+template <int NT>
+__device__ __noinline__ void phase_cross32(int q)
+{
+    inner_cross_pair<float, NT>(pargs32(), q, g_lds.cross32);
+}
+template <int NT>
+__device__ __noinline__ void phase_update32(int q, int M, unsigned long long mask)
+{
+    const BlockArgsT<float> &a = pargs32();
+    update_rows<float, NT, true, true, kPUpdLd32>(a, q, M ? a.V : a.G, 0, a.ldg / 16, mask,
+                                                reinterpret_cast<float *>(g_lds.upd.Wl), g_lds.upd.cols,
+                                                g_lds.upd.tl);
+}
+
+// One r x r FP64 product of the re-orthogonalisation, C = op(A) S B
+// (arguments in pgemm(); S = diag(+1 x p, -1 x (r - p)) on the rows of B when
+// SGN), on 16x16x4 FP64 MFMA.  Each wave forms 16 x 16 tiles of C with its
+// operands read straight from the slot (cache resident): few registers, so
+// the phase does not raise the kernel's register allocation (the grid-wide
+// product kernel holds a 64 x 64 quarter per wave instead).  SYM (with TA and
+// SGN, the symmetric X^T J X): only tiles on or above the diagonal, each
+// entry with row <= col written to both triangles, so C is exactly symmetric.
+// Per entry the k order is that of the grid-wide kernel: chunks of 4 in
+// increasing k.
+template <bool TA, bool SGN, bool SYM, int NT>
+__device__ __noinline__ void phase_gemm()
+{
+    const GemmArgs &g = pgemm();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int t16 = g.M / 16;
+    const int ntiles = t16 * t16;
+    for (int t = wave; t < ntiles; t += NT / 64) {
+        const int ti = t % t16, tj = t / t16;
+        if (SYM && ti > tj) continue;
+        const int i = ti * 16 + li, j = tj * 16 + li;
+        typedef double gd4 __attribute__((ext_vector_type(4)));
+        gd4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k0 = 0; k0 < g.K; k0 += 4) {
+            const int k = k0 + lk;
+            const double a = TA ? g.A[(size_t)i * g.lda + k] : g.A[(size_t)k * g.lda + i];
+            double b = g.B[(size_t)j * g.ldb + k];
+            if (SGN && k >= g.p) b = -b;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, acc, 0, 0, 0);
+        }
+        // register v holds C(ti 16 + lane % 16, tj 16 + lane / 16 + 4 v)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = ti * 16 + li, col = tj * 16 + lk + 4 * v;
+            if (!SYM) {
+                g.C[(size_t)col * g.ldc + row] = acc[v];
+            } else if (row <= col) {
+                g.C[(size_t)col * g.ldc + row] = acc[v];
+                g.C[(size_t)row * g.ldc + col] = acc[v];
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // Byte offsets of the parts of a slot.
 struct SlotLayout {
-    size_t G, V, P, W, d, rho, S, C, nrot, nskip, nact, ntc, maxt, active, ctl, bytes;
+    size_t G, V, P, W, d, rho, S, C, nrot, nskip, nact, ntc, maxt, active, ctl, G32, V32, T1, T2, bytes;
 };
 
 __host__ __device__ inline SlotLayout slot_layout()
@@ -120,6 +208,12 @@ __host__ __device__ inline SlotLayout slot_layout()
     s.maxt = take(sizeof(double) * kPMaxPairs);
     s.active = take(sizeof(unsigned long long) * kPMaxPairs);
     s.ctl = take(sizeof(Ctl));
+    // mixed precision: FP32 working copies, FP64 product scratch
+    const size_t mat32 = sizeof(float) * (size_t)kPMaxR * kPMaxR;
+    s.G32 = take(mat32);
+    s.V32 = take(mat32);
+    s.T1 = take(mat);
+    s.T2 = take(mat);
     s.bytes = o;
     return s;
 }
@@ -128,14 +222,14 @@ __host__ __device__ inline SlotLayout slot_layout()
 // squares its entry, the waves add in butterfly order, the four wave sums are
 // added in wave order (the order of the grouped path's norm kernel for
 // ldg <= 256 rows).
-template <int NT>
-__device__ __forceinline__ void persist_colnorm(const double *G, int ldg, int r, const int *rho, bool init,
+template <int NT, typename T>
+__device__ __forceinline__ void persist_colnorm(const T *G, int ldg, int r, const int *rho, bool init,
                                                 double *d, PersistLds &L)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int q = 0; q < r; ++q) {
         const int c = init ? q : rho[q];
-        const double x = tid < ldg ? G[(size_t)c * ldg + tid] : 0.0;  // ldg <= 256
+        const double x = tid < ldg ? (double)G[(size_t)c * ldg + tid] : 0.0;  // ldg <= 256
         const double s = wave_sum(fma(x, x, 0.0));
         if (lane == 0 && wave < 4) L.colsum[wave][q] = s;
     }
@@ -189,7 +283,8 @@ __device__ void persist_solve(const PersistArgs &pa, int z, char *slot, PersistL
     const double tol = pa.tol > 0.0 ? pa.tol : 1e-15 * n;
     const double tth = pa.tthresh > 0.0 ? pa.tthresh : sqrt(tol) / 2.0;
     double *G = reinterpret_cast<double *>(slot + sl.G);
-    double *V = pa.want_v ? reinterpret_cast<double *>(slot + sl.V) : nullptr;
+    // the mixed path carries V through its FP32 phase even when it is not returned
+    double *V = (pa.want_v || pa.mixed) ? reinterpret_cast<double *>(slot + sl.V) : nullptr;
     double *d = reinterpret_cast<double *>(slot + sl.d);
     int *rho = reinterpret_cast<int *>(slot + sl.rho);
     int4 *S = reinterpret_cast<int4 *>(slot + sl.S);
@@ -280,6 +375,213 @@ __device__ void persist_solve(const PersistArgs &pa, int z, char *slot, PersistL
     int sweeps = 0, code = 0;
     double maxt = 0.0;
     unsigned long long rot_all = 0, skip_all = 0, act_all = 0;
+    int sweeps32 = 0, nsiters = 0, restart = 0;
+    double nsprev = 2.0;
+    if (pa.mixed && status == HSVD_OK) {
+        // FP32 block sweeps on FP32 copies of G and V = I, each leaving by the
+        // switch rule of a single mixed solve; then V promoted and
+        // J-re-orthogonalised (Newton-Schulz, FP64 MFMA products) and
+        // G1 = G X, or, after a rank flag in FP32 or a residual above the
+        // accepted bound, a restart from G in FP64.  The stepper goes on
+        // from where the FP32 sweeps left it.
+        float *G32 = reinterpret_cast<float *>(slot + sl.G32);
+        float *V32 = reinterpret_cast<float *>(slot + sl.V32);
+        double *T1 = reinterpret_cast<double *>(slot + sl.T1);
+        double *T2 = reinterpret_cast<double *>(slot + sl.T2);
+        for (int e = tid; e < r * ldg; e += NT) {
+            const int c = e / ldg, row = e - c * ldg;
+            G32[e] = (float)G[e];
+            V32[e] = row == c ? 1.f : 0.f;
+        }
+        // the FP32 Gram resolves cosines down to about sqrt(r) FP32 epsilons
+        const double tol32 = fmax(tol, sqrt((double)r) * 0x1p-23);
+        if (tid == 0) {
+            BlockArgsT<float> f;
+            f.G = G32;
+            f.V = V32;
+            f.ldg = ldg;
+            f.r = r;
+            f.p = p;
+            f.nb = nb;
+            f.rho = rho;
+            f.S_in = S;
+            f.S_out = S;
+            f.ordering = pa.ordering;
+            f.step = 0;
+            f.partial = reinterpret_cast<float *>(a.partial);
+            f.splits = 1;
+            f.rows_per_split = ldg;
+            f.W = reinterpret_cast<float *>(a.W);
+            f.active = a.active;
+            f.C = a.C;
+            f.nrot = a.nrot;
+            f.nskip = a.nskip;
+            f.nact = a.nact;
+            f.ntc = a.ntc;
+            f.maxt = a.maxt;
+            f.ctl = ctl;
+            f.tol = tol32;
+            f.tthresh = sqrt(tol32) / 2.0;
+            f.inner_sweeps = 0;
+            f.nprob = 1;
+            pargs32() = f;
+        }
+        __syncthreads();
+        double pm = 1.0, pf = 1.0;
+        for (int sw = 0; sw < pa.max_sweeps; ++sw) {
+            for (int k = 0; k < steps_per_sweep; ++k) {
+                if (tid == 0) pargs32().step = k;
+                __syncthreads();
+                for (int q = 0; q < pairs; ++q) {
+                    phase_gram32(q);
+                    __syncthreads();
+                    if (k == 0)
+                        phase_circle32<NT>(q);
+                    else
+                        phase_cross32<NT>(q);
+                    __syncthreads();
+                    const unsigned long long mask = a.active[q];
+                    if (mask) {
+                        phase_update32<NT>(q, 0, mask);
+                        __syncthreads();
+                        phase_update32<NT>(q, 1, mask);
+                        __syncthreads();
+                    }
+                }
+                if (pa.ordering == HSVD_ORD_MODMOD && tid < pairs) S[tid] = modmod_next(S[tid], nb);
+                __syncthreads();
+            }
+            ++sweeps32;
+            persist_colnorm<NT>(G32, ldg, r, rho, false, d, L);
+            if (pa.sort) persist_sort(d, rho, r, p, L);
+            int c = 0;
+            unsigned long long rt = 0, sk = 0, ac = 0;
+            double mx = 0.0;
+            for (int q = 0; q < pairs; ++q) {
+                c |= a.C[q];
+                rt += a.nrot[q];
+                sk += a.nskip[q];
+                ac += a.nact[q];
+                mx = fmax(mx, a.maxt[q]);
+            }
+            const int rank = __hip_atomic_load(&ctl->rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            if (tid < pairs) {
+                a.C[tid] = 0;
+                a.nrot[tid] = 0;
+                a.nskip[tid] = 0;
+                a.nact[tid] = 0;
+                a.ntc[tid] = 0;
+                a.maxt[tid] = 0.0;
+            }
+            if (tid == 0 && rank) __hip_atomic_store(&ctl->rank, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            rot_all += rt;
+            skip_all += sk;
+            act_all += ac;
+            if (rank) {
+                // a rank failure is final only in FP64
+                restart = 1;
+                break;
+            }
+            // leave FP32 at its resolution, on stagnation, when FP32 itself
+            // converged, or by the fraction of rotating pair visits
+            const double frac = rt + sk > 0 ? (double)rt / (double)(rt + sk) : 0.0;
+            const bool stop = mx <= 3e-4 || (c & 2) == 0 || (mx < 0.1 && mx > 0.25 * pm) || frac < 0.01 ||
+                              (frac <= 1.0 / 3.0 && frac >= 0.75 * pf) || sweeps32 >= pa.max_sweeps;
+            pm = mx;
+            pf = frac;
+            if (stop) break;
+        }
+        if (!restart) {
+            for (int e = tid; e < r * ldg; e += NT) V[e] = (double)V32[e];
+            __syncthreads();
+            // Newton-Schulz: X <- X (3I - J X^T J X) / 2 while the residual
+            // max |J X^T J X - I| falls quadratically above its rounding floor
+            const double floor_ = 16.0 * n * 0x1p-53;
+            for (int it = 0; it <= 6; ++it) {
+                if (tid == 0) {
+                    GemmArgs g;
+                    g.A = V;
+                    g.B = V;
+                    g.C = T2;
+                    g.M = g.N = g.K = r;
+                    g.lda = g.ldb = g.ldc = ldg;
+                    g.p = p;
+                    pgemm() = g;
+                }
+                __syncthreads();
+                phase_gemm<true, true, true, NT>();
+                double mxr = 0.0;
+                for (int e = tid; e < r * ldg; e += NT) {
+                    const int c = e / ldg, row = e - c * ldg;
+                    const double b = T2[e];
+                    const double y = row < p ? b : -b;
+                    const double id = row == c ? 1.0 : 0.0;
+                    mxr = fmax(mxr, fabs(y - id));
+                    T2[e] = (3.0 * id - y) * 0.5;
+                }
+#pragma unroll
+                for (int m = 32; m >= 1; m >>= 1) mxr = fmax(mxr, __shfl_xor(mxr, m, 64));
+                if ((tid & 63) == 0) L.red[tid >> 6] = mxr;
+                __syncthreads();
+                double resid = L.red[0];
+                for (int w = 1; w < NT / 64; ++w) resid = fmax(resid, L.red[w]);
+                __syncthreads();
+                const bool stop = it == 6 || !(resid < 1.0) || resid <= floor_ || (it > 0 && resid > 0.25 * nsprev);
+                nsprev = resid;  // the residual of the current X: the final one once stopped
+                if (stop) break;
+                ++nsiters;
+                if (tid == 0) {
+                    GemmArgs g;
+                    g.A = V;
+                    g.B = T2;
+                    g.C = T1;
+                    g.M = g.N = g.K = r;
+                    g.lda = g.ldb = g.ldc = ldg;
+                    pgemm() = g;
+                }
+                __syncthreads();
+                phase_gemm<false, false, false, NT>();
+                for (int e = tid; e < r * ldg; e += NT) V[e] = T1[e];
+                __syncthreads();
+            }
+            const double bound = pa.reorth_accept > 0.0 ? pa.reorth_accept : 16384.0 * n * 0x1p-53;
+            if (!(nsprev <= bound)) restart = 1;
+        }
+        if (!restart) {
+            // G1 = G X
+            if (tid == 0) {
+                GemmArgs g;
+                g.A = G;
+                g.B = V;
+                g.C = T1;
+                g.M = g.N = g.K = r;
+                g.lda = g.ldb = g.ldc = ldg;
+                pgemm() = g;
+            }
+            __syncthreads();
+            phase_gemm<false, false, false, NT>();
+            for (int e = tid; e < r * ldg; e += NT) G[e] = T1[e];
+        } else {
+            // FP64 from G: the bordered working copy again, V = I, rho = id
+            for (int e = tid; e < r * ldg; e += NT) {
+                const int c = e / ldg, row = e - c * ldg;
+                double v;
+                if (c < n)
+                    v = row < n ? src[(size_t)c * n + row] : 0.0;
+                else
+                    v = row == c ? 1.0 : 0.0;
+                G[e] = v;
+                V[e] = row == c ? 1.0 : 0.0;
+            }
+            if (tid < r) rho[tid] = tid;
+        }
+        __syncthreads();
+        // the kept diagonal of the FP64 start and the sort, as after a sweep
+        persist_colnorm<NT>(G, ldg, r, rho, false, d, L);
+        if (pa.sort) persist_sort(d, rho, r, p, L);
+    }
     if (status == HSVD_OK) {
         status = HSVD_E_NOCONV;
         for (int sw = 0; sw < pa.max_sweeps; ++sw) {
@@ -367,6 +669,12 @@ __device__ void persist_solve(const PersistArgs &pa, int z, char *slot, PersistL
             const double *vc = V + (size_t)c * ldg;
             for (int row = lane; row < n; row += 64) pa.V[mo + (size_t)c * n + row] = vc[row];
         }
+    }
+    if (tid == 0 && pa.mixed) {
+        pa.sweeps32[z] = sweeps32;
+        pa.nsiters[z] = nsiters;
+        pa.restart[z] = restart;
+        pa.nsres[z] = nsprev;
     }
     if (tid == 0) {
         pa.status[z] = status;

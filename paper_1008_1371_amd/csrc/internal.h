@@ -512,6 +512,13 @@ struct PersistArgs {
     int *status = nullptr, *sweeps = nullptr, *code = nullptr;
     double *maxt = nullptr;
     unsigned long long *rot = nullptr, *skip = nullptr, *act = nullptr;
+    // mixed precision (FP32 block sweeps, J-re-orthogonalisation, FP64
+    // refinement, per problem): FP32 sweeps, Newton-Schulz corrections, final
+    // residual, FP64 restart flag per problem
+    int mixed = 0;
+    double reorth_accept = 0.0;  // <= 0: 16384 n u
+    int *sweeps32 = nullptr, *nsiters = nullptr, *restart = nullptr;
+    double *nsres = nullptr;
     char *slots = nullptr;
 };
 size_t persist_slot_bytes();

@@ -107,17 +107,25 @@ def test_batched_graph_replay_matches_eager(hsvd_ctx):
         assert a[k]["sweeps"] == b[k]["sweeps"] == c[k]["sweeps"]
 
 
-def test_batched_mixed_vs_oracle(hsvd_ctx):
+@pytest.mark.parametrize("batch_mode", [0, 1])
+def test_batched_mixed_vs_oracle(hsvd_ctx, batch_mode):
     """Mixed precision over a batch: FP32 block sweeps (each problem leaving
-    them by its own switch rule), the batched J-re-orthogonalisation, FP64
-    refinement.  Each problem against the FP64 oracle: sigma to 1e-12, U and V
-    to 10x the ordering spread (the mixed trajectory is its own)."""
+    them by its own switch rule), the J-re-orthogonalisation, FP64
+    refinement; in one persistent launch (batch_mode 0: each workgroup runs
+    the whole mixed solve of its problem) or in grouped launches (1).  Each
+    problem against the FP64 oracle: sigma to 1e-12, U and V to 10x the
+    ordering spread (the mixed trajectory is its own); the final
+    re-orthogonalisation residual within its accepted bound."""
     from parity import ordering_spread
     ns, ps, Gs = W.batch(30, lo=8, hi=200, seed_sizes=78, seed_g=9100)
-    say("batched mixed", list(ns))
-    R, res = _run(hsvd_ctx, ns, ps, Gs, precision=1)
+    say("batched mixed", batch_mode, list(ns))
+    R, res = _run(hsvd_ctx, ns, ps, Gs, precision=1, batch_mode=batch_mode)
     assert R["status"] == 0, R["statuses"]
     assert max(i["sweeps_fp32"] for i in R["infos"]) >= 1
+    U64 = np.finfo(np.float64).eps / 2
+    for k, i in enumerate(R["infos"]):
+        if not i["fp64_restart"]:
+            assert i["reorth_resid"] <= 16384 * ns[k] * U64, (k, i["reorth_resid"])
     for k, (n, p, G) in enumerate(zip(ns, ps, Gs)):
         spread, ref = ordering_spread(G, int(p), block=32)
         e = compare(res[k], ref, int(p))
@@ -128,7 +136,8 @@ def test_batched_mixed_vs_oracle(hsvd_ctx):
         pins.check_invariants(G, int(p), r, tol=1e-15 * n)
 
 
-def test_batched_mixed_edge_and_no_v(hsvd_ctx):
+@pytest.mark.parametrize("batch_mode", [0, 1])
+def test_batched_mixed_edge_and_no_v(hsvd_ctx, batch_mode):
     """Mixed batch with n = 1, definite signatures and a rank-deficient
     problem (failure local to it), and without V: sigma equal to the run with
     V."""
@@ -137,7 +146,7 @@ def test_batched_mixed_edge_and_no_v(hsvd_ctx):
     Gs[3][:, 5] = Gs[3][:, 9]  # duplicate columns: numerically rank deficient
     ns = np.array([1, 7, 64, 65, 130], np.int32)
     ps = np.array([1, 0, 64, 30, 65], np.int32)
-    R, res = _run(hsvd_ctx, ns, ps, Gs, precision=1)
+    R, res = _run(hsvd_ctx, ns, ps, Gs, precision=1, batch_mode=batch_mode)
     say("mixed edge statuses", R["statuses"], "sweeps", R["sweeps"], [i["sweeps_fp32"] for i in R["infos"]],
         "restarts", [i["fp64_restart"] for i in R["infos"]])
     from paper_1008_1371_amd import hsvd as H
@@ -146,7 +155,7 @@ def test_batched_mixed_edge_and_no_v(hsvd_ctx):
     for k in (0, 1, 2, 4):
         ref = oracle.hsvd(Gs[k], int(ps[k]))
         assert np.allclose(np.sort(res[k]["sigma"]), np.sort(ref["sigma"]), rtol=1e-12, atol=0)
-    R2, res2 = _run(hsvd_ctx, ns, ps, Gs, precision=1, want_v=0)
+    R2, res2 = _run(hsvd_ctx, ns, ps, Gs, precision=1, want_v=0, batch_mode=batch_mode)
     for k in (0, 1, 2, 4):
         assert np.allclose(np.sort(res2[k]["sigma"]), np.sort(res[k]["sigma"]), rtol=1e-12, atol=0)
 
@@ -246,3 +255,33 @@ def test_batched_persistent_widths_bit_identical(tmp_path, monkeypatch):
         assert best in (256, 512, 1024) and all(v > 0 for v in ms.values())
         assert best == min(ms, key=ms.get)
         assert '"threads": %d' % best in cache.read_text()
+
+
+def test_batched_persistent_mixed_widths_bit_identical(tmp_path, monkeypatch):
+    """Mixed precision in the persistent launch: the workgroup width does not
+    change the results (every phase, the re-orthogonalisation products
+    included, has width-independent arithmetic), and the FP64 restart of a
+    problem whose FP32 phase meets a rank flag stays local to it."""
+    from paper_1008_1371_amd import hsvd as H
+    ns, ps, Gs = W.batch(48, seed_sizes=85, seed_g=9500)
+    ns[0] = 256
+    Gs[0] = np.random.Generator(np.random.PCG64(4)).standard_normal((256, 256))
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("HSVD_AUTOTUNE_CACHE", str(cache))
+    ref = None
+    for threads in (256, 512, 1024):
+        cache.write_text('{"entries": [{"batched_bucket": 3, "threads": %d}]}' % threads)
+        with H.Context(0) as ctx:
+            R, _ = _run(ctx, ns, ps, Gs, precision=1, batch_mode=0)
+            P = _packed(R)
+        say("mixed persistent width", threads, "status", R["status"], "fp32 sweeps",
+            max(i["sweeps_fp32"] for i in R["infos"]), "restarts", sum(i["fp64_restart"] for i in R["infos"]))
+        assert R["status"] == 0
+        if ref is None:
+            ref = (R, P)
+            continue
+        assert np.array_equal(R["sweeps"], ref[0]["sweeps"])
+        for key in ("sweeps_fp32", "reorth_iters", "fp64_restart", "reorth_resid", "rotations"):
+            assert [i[key] for i in R["infos"]] == [i[key] for i in ref[0]["infos"]], (threads, key)
+        for k in ("sigma", "lam", "U", "V"):
+            assert np.array_equal(P[k], ref[1][k]), (threads, k)
