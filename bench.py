@@ -36,16 +36,16 @@ FP32_PEAK_TFLOPS = 157.3
 MEASURED_TRAFFIC = {
     "workload": "colscaled4096",
     "mode": "mixed",
-    "sources": ["paper_1008_1371_amd/csrc/block_kernels.hip", "paper_1008_1371_amd/csrc/api.hip",
-                "paper_1008_1371_amd/csrc/internal.h"],
-    "sha256": "65f8490671b1d70431ef341be2e09d3f5821553fa2c13ca207732ee78b3e85c0",
+    "sources": ["paper_1008_1371_amd/csrc/block_kernels.hip", "paper_1008_1371_amd/csrc/block_device.h",
+                "paper_1008_1371_amd/csrc/api.hip", "paper_1008_1371_amd/csrc/internal.h"],
+    "sha256": "2e3da0d6296ea4cfdcb4c08561c22c905f3991b7442b09cfa6a60098d90c5e86",
     "bytes_per_launch": {
-        "block_gram_kernel<float>": (32866.6 * 2.0 + 5120.0 * 1.0) * 1024,
-        "block_inner_kernel<float>": (22137.3 * 2.0 + 37627.1 * 1.0) * 1024,
-        "block_update_kernel<float>": (18688.0 * 2.0 + 36674.5 * 1.0) * 1024,
-        "block_gram_kernel<double>": (65598.5 * 2.0 + 10240.0 * 1.0) * 1024,
-        "block_inner_kernel<double>": (25032.9 * 2.0 + 37493.6 * 1.0) * 1024,
-        "block_update_kernel<double>": (18354.2 * 2.0 + 35512.8 * 1.0) * 1024,
+        "block_gram_kernel<float>": (32857.3 * 2.0 + 5120.0 * 1.0) * 1024,
+        "block_inner_kernel<float>": (22296.8 * 2.0 + 37595.4 * 1.0) * 1024,
+        "block_update_kernel<float>": (18465.7 * 2.0 + 36542.0 * 1.0) * 1024,
+        "block_gram_kernel<double>": (65593.5 * 2.0 + 10240.0 * 1.0) * 1024,
+        "block_inner_kernel<double>": (27494.8 * 2.0 + 37493.5 * 1.0) * 1024,
+        "block_update_kernel<double>": (18361.2 * 2.0 + 35512.7 * 1.0) * 1024,
     },
 }
 

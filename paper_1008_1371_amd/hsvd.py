@@ -11,6 +11,7 @@ loudly when it has not been built (``python -m paper_1008_1371_amd.build``).
 """
 from __future__ import annotations
 
+import collections.abc
 import ctypes
 import os
 import re
@@ -66,6 +67,28 @@ class hsvd_info(ctypes.Structure):
             v = getattr(self, k)
             out[k] = list(v) if hasattr(v, "__len__") else v
         return out
+
+
+class InfoList(collections.abc.Sequence):
+    """The per-problem hsvd_info of a batched solve as a sequence of dicts,
+    each converted when it is accessed (converting 10^4 of them up front
+    takes longer than a small batch's solve)."""
+
+    def __init__(self, arr, n):
+        self._a = arr
+        self._n = n
+
+    def __len__(self):
+        return self._n
+
+    def __getitem__(self, k):
+        if isinstance(k, slice):
+            return [self._a[i].as_dict() for i in range(*k.indices(self._n))]
+        if k < 0:
+            k += self._n
+        if not 0 <= k < self._n:
+            raise IndexError(k)
+        return self._a[k].as_dict()
 
 
 _lib = None
@@ -289,8 +312,9 @@ def hsvd_solve_batched(ctx: Context, ns, ps, G_packed, offs, voffs, params: hsvd
     each column-major G_k in G_packed, offset of sigma_k), passed to the
     library as device arrays.  G_packed: float64 CUDA tensor with all inputs.
     Returns a dict with the packed outputs (sigma, U, V, lam: tensors or
-    None), the per-problem infos (a list of dicts) and, for convenience, their
-    statuses and FP64 sweep counts as NumPy arrays."""
+    None), the per-problem infos (a sequence of dicts, each converted when
+    accessed) and, for convenience, their statuses and FP64 sweep counts as
+    NumPy arrays."""
     import numpy as np
     import torch
     L = lib()
@@ -324,10 +348,11 @@ def hsvd_solve_batched(ctx: Context, ns, ps, G_packed, offs, voffs, params: hsvd
                               ctypes.byref(prm), _ptr(sigma), _ptr(U), _ptr(V), _ptr(lam), infos)
     if check and st != OK:
         raise HsvdError(st, "hsvd_solve_batched")
-    info_list = [infos[k].as_dict() for k in range(batch)]
-    status = np.array([i["status"] for i in info_list], dtype=np.int32)
-    sweeps = np.array([i["sweeps"] for i in info_list], dtype=np.int32)
-    return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, infos=info_list, statuses=status, sweeps=sweeps)
+    rec = np.ctypeslib.as_array(infos)[:batch]
+    status = rec["status"].astype(np.int32)
+    sweeps = rec["sweeps"].astype(np.int32)
+    return dict(status=st, sigma=sigma, U=U, V=V, lam=lam, infos=InfoList(infos, batch), statuses=status,
+                sweeps=sweeps)
 
 
 def hsvd_pair_params(ctx: Context, aii, ajj, aij, hyp, tol: float, t_thresh: float, block=False):
