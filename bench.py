@@ -335,8 +335,10 @@ def timed(H, ctx, G, p, prm, out, steps, warmup, check):
 
 def batched_line(H, W, ctx, count):
     """The batched solver on `count` Gaussian problems, n ~ U{8..256}, FP64
-    and mixed precision, each in one persistent launch (its width autotuned
-    first) and, for comparison, in launches grouped by bordered order."""
+    and mixed precision, with the sweep schedule and the persistent kernel's
+    width the autotuner picks (tuned first, outside the timed runs), and each
+    schedule on its own for comparison: one persistent launch, and launches
+    grouped by bordered order."""
     import numpy as np
     import torch
     ns, ps, Gs = W.batch(count)
@@ -347,7 +349,10 @@ def batched_line(H, W, ctx, count):
     # the persistent kernel's width for this size mix (outside the timed runs)
     best, widths = H.hsvd_autotune_batched(ctx, ns, ps)
     out["persistent_width"] = {"threads": best, "autotune_ms": widths}
-    for name, prec, mode in (("fp64", H.FP64, 0), ("mixed", H.MIXED, 0), ("fp64_grouped", H.FP64, 1),
+    out["schedule"] = {name: ("persistent", "grouped")[H.hsvd_batched_schedule(ctx, prec)]
+                       for name, prec in (("fp64", H.FP64), ("mixed", H.MIXED))}
+    for name, prec, mode in (("fp64", H.FP64, 2), ("mixed", H.MIXED, 2), ("fp64_persistent", H.FP64, 0),
+                             ("fp64_grouped", H.FP64, 1), ("mixed_persistent", H.MIXED, 0),
                              ("mixed_grouped", H.MIXED, 1)):
         prm = H.hsvd_default_params(precision=prec, batch_mode=mode)
         H.hsvd_solve_batched(ctx, ns, ps, Gd, offs, voffs, prm)  # warm-up

@@ -83,14 +83,17 @@ typedef struct {
     double reorth_accept; /* mixed path: largest accepted max |J X^T J X - I| after the
                         Newton-Schulz J-re-orthogonalisation of V (above it the
                         solve restarts from G in FP64); <= 0: 16384 n u, u = 2^-53  */
-    int batch_mode;  /* hsvd_solve_batched: 0 = every block-oriented problem with
-                        n <= 256, FP64 or mixed, in one persistent launch (the
-                        others, and the full-block method, in launches grouped by
-                        bordered order); 1 = grouped launches for every problem.
-                        FP64: the two give bit-identical results.  Mixed: each
-                        gives a valid mixed trajectory (the FP64 sweeps of a
-                        problem start at the stepper phase its own FP32 sweeps
-                        left, in the grouped launches at the group's)          */
+    int batch_mode;  /* hsvd_solve_batched, the sweep schedule: 0 = every
+                        block-oriented problem with n <= 256, FP64 or mixed, in
+                        one persistent launch (the others, and the full-block
+                        method, in launches grouped by bordered order); 1 =
+                        grouped launches for every problem; 2 (default) = the
+                        schedule hsvd_autotune_batched chose for the precision,
+                        0 before tuning.  FP64: 0 and 1 give bit-identical
+                        results.  Mixed: each gives a valid mixed trajectory (the
+                        FP64 sweeps of a problem start at the stepper phase its
+                        own FP32 sweeps left, in the grouped launches at the
+                        group's)                                               */
     int persistent;  /* pairwise path: 0 = one launch per parallel step (replayed from a
                         HIP graph when graph = 1) and the stop rule checked on the host
                         after every sweep; 1 = all sweeps in one persistent cooperative
@@ -272,13 +275,27 @@ hsvd_status hsvd_autotune(hsvd_ctx *ctx, int n, int *best_algo, int *best_wg);
  * (128, 192], (192, 256]) in the context; later hsvd_solve_batched calls whose
  * persistent problems fall in that bucket use it (default before tuning: 256).
  * The results of a batched solve do not depend on the width (bit-identical).
- * With HSVD_AUTOTUNE_CACHE set the choice is written to that file too.
+ * Then, with the chosen width, it times the two sweep schedules (one persistent
+ * launch, launches grouped by order; batch_mode 0 and 1) in FP64 and in mixed
+ * precision on the whole batch's orders (seeded synthetic entries as above:
+ * the grouped launches gain with the number of problems per group, so a sample
+ * would not tell) and keeps the faster per precision for hsvd_solve_batched
+ * calls with batch_mode = 2 (hsvd_batched_schedule reports the choice).  Its
+ * inputs and outputs take three times the batch's packed size in the context's
+ * auxiliary device buffer, kept until hsvd_destroy.  With HSVD_AUTOTUNE_CACHE
+ * set the choices are written to that file too.
  *   n, p          device or host arrays of `batch` entries (as hsvd_solve_batched).
  *   best_threads  host, may be NULL: the chosen width.
  *   ms            host, may be NULL: 3 floats, the time of each width (ms).
  * Errors: HSVD_E_INVAL (no problem with n <= 256, or bad n / p).  Synchronises. */
 hsvd_status hsvd_autotune_batched(hsvd_ctx *ctx, int batch, const int *n, const int *p, int *best_threads,
                                   float *ms);
+
+/* The sweep schedule hsvd_solve_batched takes with batch_mode = 2 for
+ * `precision` (HSVD_FP64 or HSVD_MIXED): *mode = 0 (one persistent launch),
+ * 1 (launches grouped by order), or -1 (not tuned: the persistent launch).
+ * Errors: HSVD_E_INVAL (ctx or mode NULL, another precision). */
+hsvd_status hsvd_batched_schedule(const hsvd_ctx *ctx, int precision, int *mode);
 
 /* ---- Diagnostics: the individual steps of the path on caller data ---- */
 

@@ -36,6 +36,9 @@ struct hsvd_ctx {
     // the largest order in the launch ((0, 64], (64, 128], (128, 192],
     // (192, 256]); 0 = the default
     int persist_threads[4] = {0, 0, 0, 0};
+    // sweep schedule of batch_mode 2 per precision (FP64, mixed): 0 = one
+    // persistent launch, 1 = launches grouped by order; -1 = not tuned
+    int batch_sched[2] = {-1, -1};
 };
 
 // Fixed device scratch of hsvd_solve_noalloc: the workspace of one solve,
@@ -104,6 +107,13 @@ void tune_load(hsvd_ctx *ctx)
             (t == 256 || t == 512 || t == 1024))
             ctx->persist_threads[b] = t;
     }
+    // {"batched_schedule": P, "mode": M}
+    for (const char *q = strstr(buf, "\"batched_schedule\""); q; q = strstr(q + 1, "\"batched_schedule\"")) {
+        int pr = -1, m = -1;
+        if (sscanf(q, "\"batched_schedule\": %d, \"mode\": %d", &pr, &m) == 2 && (pr == 0 || pr == 1) &&
+            (m == 0 || m == 1))
+            ctx->batch_sched[pr] = m;
+    }
 }
 
 void tune_save(const hsvd_ctx *ctx)
@@ -123,6 +133,11 @@ void tune_save(const hsvd_ctx *ctx)
     for (int b = 0; b < 4; ++b) {
         if (!ctx->persist_threads[b]) continue;
         fprintf(f, "%s\n  {\"batched_bucket\": %d, \"threads\": %d}", first ? "" : ",", b, ctx->persist_threads[b]);
+        first = false;
+    }
+    for (int pr = 0; pr < 2; ++pr) {
+        if (ctx->batch_sched[pr] < 0) continue;
+        fprintf(f, "%s\n  {\"batched_schedule\": %d, \"mode\": %d}", first ? "" : ",", pr, ctx->batch_sched[pr]);
         first = false;
     }
     fprintf(f, "\n]}\n");
@@ -294,7 +309,7 @@ void hsvd_default_params(hsvd_params *prm)
     prm->graph = 1;
     prm->inner_sweeps = 0;
     prm->reorth_accept = 0.0;
-    prm->batch_mode = 0;
+    prm->batch_mode = 2;
     prm->persistent = 0;
 }
 
@@ -1446,6 +1461,7 @@ extern "C" hsvd_status hsvd_autotune_batched(hsvd_ctx *ctx, int batch, const int
     const hipEvent_t ev[2] = {ctx->events[nev], ctx->events[nev + 1]};
     hsvd_params prm;
     hsvd_default_params(&prm);
+    prm.batch_mode = 0;  // the widths are the persistent launch's
     const int bucket = std::min(3, (nmax - 1) / 64);
     const int saved = ctx->persist_threads[bucket];
     const int cands[3] = {256, 512, 1024};
@@ -1475,8 +1491,57 @@ extern "C" hsvd_status hsvd_autotune_batched(hsvd_ctx *ctx, int batch, const int
         }
     }
     ctx->persist_threads[bucket] = best;
+    // The sweep schedule per precision, with the chosen width: one persistent
+    // launch against launches grouped by order, timed on the whole batch (the
+    // grouped launches gain with the number of problems per group, so a
+    // sample would not tell).
+    std::vector<long long> aoff(batch), avoff(batch);
+    long long atot = 0, atotv = 0;
+    for (int k = 0; k < batch; ++k) {
+        if (n[k] < 1 || n[k] > 1024 || p[k] < 0 || p[k] > n[k]) return HSVD_E_INVAL;
+        aoff[k] = atot;
+        avoff[k] = atotv;
+        atot += (long long)n[k] * n[k];
+        atotv += n[k];
+    }
+    size_t oa = 0;
+    const size_t a_G = take_bytes(oa, sizeof(double) * atot), a_U = take_bytes(oa, sizeof(double) * atot);
+    const size_t a_V = take_bytes(oa, sizeof(double) * atot), a_s = take_bytes(oa, sizeof(double) * atotv);
+    const hsvd_status sa2 = ensure_aux(ctx, oa);
+    if (sa2 != HSVD_OK) return sa2;
+    char *abase = static_cast<char *>(ctx->aux);
+    double *AG = reinterpret_cast<double *>(abase + a_G);
+    for (int k = 0; k < batch; ++k)
+        HSVD_TRY(launch_synth(st, AG + aoff[k], n[k], 0x5C4EDull + (unsigned long long)k));
+    for (int pr = 0; pr < 2; ++pr) {
+        float sched_ms[2] = {0.f, 0.f};
+        for (int mode = 0; mode < 2; ++mode) {
+            hsvd_params q = prm;
+            q.precision = pr ? HSVD_MIXED : HSVD_FP64;
+            q.batch_mode = mode;
+            for (int rep = 0; rep < 2; ++rep) {  // the first run also warms up
+                HSVD_TRY(hipEventRecord(ev[0], st));
+                const hsvd_status s = hsvd_solve_batched(
+                    ctx, batch, n.data(), p.data(), aoff.data(), avoff.data(), AG, &q,
+                    reinterpret_cast<double *>(abase + a_s), reinterpret_cast<double *>(abase + a_U),
+                    reinterpret_cast<double *>(abase + a_V), nullptr, nullptr);
+                if (s != HSVD_OK && s != HSVD_E_NOCONV) return s;
+                HSVD_TRY(hipEventRecord(ev[1], st));
+                HSVD_TRY(hipEventSynchronize(ev[1]));
+                HSVD_TRY(hipEventElapsedTime(&sched_ms[mode], ev[0], ev[1]));
+            }
+        }
+        ctx->batch_sched[pr] = sched_ms[1] < sched_ms[0] ? 1 : 0;
+    }
     tune_save(ctx);
     if (best_threads) *best_threads = best;
+    return HSVD_OK;
+}
+
+extern "C" hsvd_status hsvd_batched_schedule(const hsvd_ctx *ctx, int precision, int *mode)
+{
+    if (!ctx || !mode || (precision != HSVD_FP64 && precision != HSVD_MIXED)) return HSVD_E_INVAL;
+    *mode = ctx->batch_sched[precision == HSVD_MIXED ? 1 : 0];
     return HSVD_OK;
 }
 
@@ -1766,7 +1831,7 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
     if (prm.ordering != HSVD_ORD_MODMOD && prm.ordering != HSVD_ORD_ROUNDROBIN) return HSVD_E_INVAL;
     if (prm.block != 0 && prm.block != block_width()) return HSVD_E_INVAL;
     if (prm.inner_sweeps < 0 || prm.inner_sweeps > 100) return HSVD_E_INVAL;
-    if (prm.batch_mode != 0 && prm.batch_mode != 1) return HSVD_E_INVAL;
+    if (prm.batch_mode < 0 || prm.batch_mode > 2) return HSVD_E_INVAL;
     const bool want_v = prm.want_v != 0;
     if (V && !want_v) return HSVD_E_INVAL;
     // the mixed path carries V through its FP32 phase even when it is not returned
@@ -1795,7 +1860,10 @@ extern "C" hsvd_status hsvd_solve_batched(hsvd_ctx *ctx, int batch, const int *n
     // rounded up to 2b, one sequence of launches per group
     std::vector<int> pers;
     std::vector<std::vector<int>> groups(1024 / (2 * b) + 1);
-    const bool persist_ok = prm.inner_sweeps == 0 && prm.batch_mode == 0;
+    // batch_mode 2: the schedule the autotuner chose for this precision, else
+    // the persistent launch
+    const int sched = prm.batch_mode == 2 ? std::max(0, ctx->batch_sched[mixed ? 1 : 0]) : prm.batch_mode;
+    const bool persist_ok = prm.inner_sweeps == 0 && sched == 0;
     for (int k = 0; k < batch; ++k) {
         if (persist_ok && n[k] <= kPersistMaxOrder)
             pers.push_back(k);

@@ -129,12 +129,13 @@ def lib():
     L.hsvd_solve_batched.argtypes = [vp, ip, vp, vp, vp, vp, vp, ctypes.POINTER(hsvd_params), vp, vp,
                                      vp, vp, vp]
     L.hsvd_autotune_batched.argtypes = [vp, ip, vp, vp, ctypes.POINTER(ip), vp]
+    L.hsvd_batched_schedule.argtypes = [vp, ip, ctypes.POINTER(ip)]
     L.hsvd_version.restype = ctypes.c_char_p
     for name in ("hsvd_init", "hsvd_destroy", "hsvd_solve", "hsvd_solve_noalloc", "hsvd_autotune",
                  "hsvd_pair_params",
                  "hsvd_block_pair_params",
                  "hsvd_pivot_trace", "hsvd_sort_diag", "hsvd_block_trace", "hsvd_solve_batched",
-                 "hsvd_autotune_batched"):
+                 "hsvd_autotune_batched", "hsvd_batched_schedule"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -289,10 +290,19 @@ def hsvd_autotune(ctx: Context, n: int):
     return a.value, w.value
 
 
+def hsvd_batched_schedule(ctx: Context, precision: int) -> int:
+    """The sweep schedule batch_mode 2 takes for `precision`: 0 persistent,
+    1 grouped, -1 not tuned."""
+    m = ctypes.c_int()
+    _check(lib().hsvd_batched_schedule(ctx.handle, int(precision), ctypes.byref(m)), "hsvd_batched_schedule")
+    return m.value
+
+
 def hsvd_autotune_batched(ctx: Context, ns, ps):
     """Times the persistent batched kernel's widths (256 / 512 / 1024 threads
     per problem) on a sample of the given orders and keeps the fastest for
-    their size bucket; returns (threads, {threads: ms})."""
+    their size bucket, then the two sweep schedules per precision; returns
+    (threads, {threads: ms})."""
     import numpy as np
     n_a = np.ascontiguousarray(ns, dtype=np.int32)
     p_a = np.ascontiguousarray(ps, dtype=np.int32)

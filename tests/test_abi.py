@@ -34,7 +34,7 @@ def test_defaults_and_argument_checks_without_gpu():
     prm = H.hsvd_default_params()
     assert (prm.precision, prm.algo, prm.ordering, prm.sort, prm.want_v, prm.max_sweeps,
             prm.graph, prm.inner_sweeps, prm.reorth_accept, prm.batch_mode, prm.persistent) == \
-        (H.FP64, H.AUTO, H.MODMOD, 1, 1, 100, 1, 0, 0.0, 0, 0)
+        (H.FP64, H.AUTO, H.MODMOD, 1, 1, 100, 1, 0, 0.0, 2, 0)
     assert H.hsvd_version().startswith("hsvd-gfx950")
     # argument errors are reported before any device call
     assert L.hsvd_init(None, 0, None) == H.E_INVAL

@@ -255,6 +255,18 @@ def test_batched_persistent_widths_bit_identical(tmp_path, monkeypatch):
         assert best in (256, 512, 1024) and all(v > 0 for v in ms.values())
         assert best == min(ms, key=ms.get)
         assert '"threads": %d' % best in cache.read_text()
+        # the sweep schedule per precision, which batch_mode 2 (the default)
+        # then takes: the same results as asking for that schedule
+        for prec in (H.FP64, H.MIXED):
+            sched = H.hsvd_batched_schedule(ctx, prec)
+            say("autotuned schedule", prec, ("persistent", "grouped")[sched])
+            assert sched in (0, 1)
+            assert '"batched_schedule": %d, "mode": %d' % (prec, sched) in cache.read_text()
+            Ra, _ = _run(ctx, ns, ps, Gs, precision=prec)
+            Rb, _ = _run(ctx, ns, ps, Gs, precision=prec, batch_mode=sched)
+            Pa, Pb = _packed(Ra), _packed(Rb)
+            for k in ("sigma", "lam", "U", "V"):
+                assert np.array_equal(Pa[k], Pb[k]), (prec, k)
 
 
 def test_batched_persistent_mixed_widths_bit_identical(tmp_path, monkeypatch):
