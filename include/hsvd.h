@@ -203,6 +203,9 @@ hsvd_status hsvd_solve(hsvd_ctx *ctx, const double *G, int lda, const signed cha
  *    for FP64, about 54 n^2 for HSVD_MIXED; every path fits for n <= 1024).
  *  - prm->graph is ignored (stream launches), and hsvd_info carries no times
  *    (ms_total and kernel_ms are zero).
+ *  - prm->persistent must be 0 (HSVD_E_INVAL otherwise): the persistent
+ *    pairwise kernel is a cooperative launch, which the runtime may back
+ *    with allocations of its own.
  *  - Every call on one device uses that device's one array, whatever the
  *    context: calls that overlap on one device (two host threads, or two
  *    contexts on different streams) race and corrupt each other.  Calls on one

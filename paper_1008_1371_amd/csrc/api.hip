@@ -1342,6 +1342,9 @@ extern "C" hsvd_status hsvd_solve_noalloc(hsvd_ctx *ctx, const double *G, int ld
     hsvd_params prm;
     if (prm_in) prm = *prm_in;
     else hsvd_default_params(&prm);
+    // the persistent pairwise kernel is a cooperative launch, which the
+    // runtime may back with allocations of its own
+    if (prm.persistent != 0) return HSVD_E_INVAL;
     HSVD_TRY(hipSetDevice(ctx->device));
     void *ptr = scratch_address(ctx->device);
     if (!ptr) return HSVD_E_DEVICE;

@@ -74,6 +74,10 @@ def test_noalloc_rejects_what_does_not_fit(hsvd_ctx):
     G = torch.zeros((n, n), dtype=torch.float64, device="cuda:0")
     R = H.hsvd_solve_noalloc(hsvd_ctx, G, n // 2, H.hsvd_default_params(precision=H.MIXED), check=False)
     assert R["status"] == H.E_SIZE
+    # the persistent pairwise kernel (a cooperative launch) is not offered here
+    R = H.hsvd_solve_noalloc(hsvd_ctx, G[:64, :64].contiguous(), 32,
+                             H.hsvd_default_params(algo=H.PAIRWISE, persistent=1), check=False)
+    assert R["status"] == H.E_INVAL
     Gs = W.gaussian(64, seed=5)
     ref, got = _pair(hsvd_ctx, Gs, 32, H.hsvd_default_params())
     assert got["status"] == H.OK
