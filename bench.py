@@ -38,14 +38,14 @@ MEASURED_TRAFFIC = {
     "mode": "mixed",
     "sources": ["paper_1008_1371_amd/csrc/block_kernels.hip", "paper_1008_1371_amd/csrc/block_device.h",
                 "paper_1008_1371_amd/csrc/api.hip", "paper_1008_1371_amd/csrc/internal.h"],
-    "sha256": "2e3da0d6296ea4cfdcb4c08561c22c905f3991b7442b09cfa6a60098d90c5e86",
+    "sha256": "fb28f988831edf530ed1c4735b5c0d20b917fc5fd2a6fb4a1dcfee3ac35a98b7",
     "bytes_per_launch": {
-        "block_gram_kernel<float>": (32857.3 * 2.0 + 5120.0 * 1.0) * 1024,
-        "block_inner_kernel<float>": (22296.8 * 2.0 + 37595.4 * 1.0) * 1024,
-        "block_update_kernel<float>": (18465.7 * 2.0 + 36542.0 * 1.0) * 1024,
+        "block_gram_kernel<float>": (32858.3 * 2.0 + 5120.0 * 1.0) * 1024,
+        "block_inner_kernel<float>": (22293.3 * 2.0 + 37590.1 * 1.0) * 1024,
+        "block_update_kernel<float>": (20432.7 * 2.0 + 36758.4 * 1.0) * 1024,
         "block_gram_kernel<double>": (65593.5 * 2.0 + 10240.0 * 1.0) * 1024,
-        "block_inner_kernel<double>": (27494.8 * 2.0 + 37493.5 * 1.0) * 1024,
-        "block_update_kernel<double>": (18361.2 * 2.0 + 35512.7 * 1.0) * 1024,
+        "block_inner_kernel<double>": (27517.2 * 2.0 + 37493.5 * 1.0) * 1024,
+        "block_update_kernel<double>": (18363.2 * 2.0 + 35512.7 * 1.0) * 1024,
     },
 }
 
