@@ -34,6 +34,7 @@
 // counters; FP32 copies and FP64 product scratch for mixed precision), sized
 // for the largest order the kernel takes (n <= 256).
 #include "block_device.h"
+#include "gemm_device.h"
 
 namespace hsvd {
 
@@ -52,6 +53,7 @@ union PersistLds {
     CircleLds circle;
     CrossLds<double> cross;
     CrossLds<float> cross32;
+    gemm::GemmLds gemm;
     double red[kGramRed];
     struct {
         double Wl[kB2 * kPUpdLd];
@@ -133,48 +135,20 @@ __device__ __noinline__ void phase_update32(int q, int M, unsigned long long mas
 
 // One r x r FP64 product of the re-orthogonalisation, C = op(A) S B
 // (arguments in pgemm(); S = diag(+1 x p, -1 x (r - p)) on the rows of B when
-// SGN), on 16x16x4 FP64 MFMA.  Each wave forms 16 x 16 tiles of C with its
-// operands read straight from the slot (cache resident): few registers, so
-// the phase does not raise the kernel's register allocation (the grid-wide
-// product kernel holds a 64 x 64 quarter per wave instead).  SYM (with TA and
-// SGN, the symmetric X^T J X): only tiles on or above the diagonal, each
-// entry with row <= col written to both triangles, so C is exactly symmetric.
-// Per entry the k order is that of the grid-wide kernel: chunks of 4 in
-// increasing k.
+// SGN), tile by tile (128 x 128, at most 2 x 2 of them) with the grid-wide
+// product kernel's tile code (gemm_device.h) on the first 256 threads: the
+// same arithmetic as the grouped launches' products.  SYM: the tiles on and
+// above the diagonal, each written to both triangles.
 template <bool TA, bool SGN, bool SYM, int NT>
 __device__ __noinline__ void phase_gemm()
 {
     const GemmArgs &g = pgemm();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    const int t16 = g.M / 16;
-    const int ntiles = t16 * t16;
-    for (int t = wave; t < ntiles; t += NT / 64) {
-        const int ti = t % t16, tj = t / t16;
-        if (SYM && ti > tj) continue;
-        const int i = ti * 16 + li, j = tj * 16 + li;
-        typedef double gd4 __attribute__((ext_vector_type(4)));
-        gd4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int k0 = 0; k0 < g.K; k0 += 4) {
-            const int k = k0 + lk;
-            const double a = TA ? g.A[(size_t)i * g.lda + k] : g.A[(size_t)k * g.lda + i];
-            double b = g.B[(size_t)j * g.ldb + k];
-            if (SGN && k >= g.p) b = -b;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, acc, 0, 0, 0);
+    const int tiles = (g.M + gemm::kTM - 1) / gemm::kTM;
+    for (int tn = 0; tn < tiles; ++tn)
+        for (int tm = 0; tm < tiles; ++tm) {
+            if (SYM && tm > tn) continue;
+            gemm::gemm_tile<TA, SGN, SYM, (NT > 256)>(g, 0, 0, 0, tm, tn, g_lds.gemm);
         }
-        // register v holds C(ti 16 + lane % 16, tj 16 + lane / 16 + 4 v)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = ti * 16 + li, col = tj * 16 + lk + 4 * v;
-            if (!SYM) {
-                g.C[(size_t)col * g.ldc + row] = acc[v];
-            } else if (row <= col) {
-                g.C[(size_t)col * g.ldc + row] = acc[v];
-                g.C[(size_t)row * g.ldc + col] = acc[v];
-            }
-        }
-    }
     __syncthreads();
 }
 
