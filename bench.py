@@ -91,6 +91,9 @@ def parse():
     ap.add_argument("--persistent", type=int, default=0, choices=[0, 1, 2],
                     help="pairwise path: 0 one launch per step (graph replay), 1 one persistent launch with "
                          "per-column readiness between steps, 2 the same with a grid barrier per step")
+    ap.add_argument("--also", default="graded4096_k1e6_p0.5",
+                    help="a second workload timed beside the headline (mixed and FP64, errors against its stored "
+                         "oracle result); empty: none")
     ap.add_argument("--inner-sweeps", type=int, default=0,
                     help="block modes: 0 = block-oriented method; k > 0 = full-block method with at most "
                          "k inner sweeps per pivot block")
@@ -498,6 +501,32 @@ def main():
         line["oracle_spread"] = {k: {q: m[k][q] for q in ("sigma_norm", "sigma_max", "U", "V")} |
                                  {"U_col_max": max(m[k]["U_cols"]), "V_col_max": max(m[k]["V_cols"])}
                                  for k in ("twin", "ordering_spread")}
+    if args.also and args.also != args.workload and args.inner_sweeps == 0 and args.block != 64 \
+            and args.mode in ("both", "mixed", "fp64") and not args.no_v and args.max_sweeps <= 0:
+        # the second workload: the graded-spectrum matrix of the paper's
+        # experiments at n = 4096 (kappa 1e6, p = n/2), both paths, each
+        # against the oracle's stored result of the same input
+        G2_np, p2 = W.workload(args.also)
+        n2 = G2_np.shape[0]
+        G2 = torch.from_numpy(np.asfortranarray(G2_np)).to(dev)
+        out2 = dict(sigma=torch.empty(n2, dtype=torch.float64, device=dev),
+                    U=torch.empty((n2, n2), dtype=torch.float64, device=dev).t(),
+                    V=torch.empty((n2, n2), dtype=torch.float64, device=dev).t(),
+                    **{"lambda": torch.empty(n2, dtype=torch.float64, device=dev)},
+                    perm=torch.empty(n2, dtype=torch.int32, device=dev))
+        fx2 = oracle_fixture(args.also)
+        also = {"n": n2, "p": p2}
+        for mode in ("mixed", "fp64"):
+            m_ms, m_infos, R2 = timed(H, ctx, G2, p2, params(mode), out2, args.steps, args.warmup, True)
+            also[mode] = {"ms_per_step": m_ms, "solves_per_s": 1000.0 / m_ms, "sweeps": m_infos[-1]["sweeps"],
+                          "sweeps_fp32": m_infos[-1]["sweeps_fp32"]}
+            if fx2 is not None and not args.no_accuracy:
+                also[mode]["vs_oracle"] = vs_oracle(fx2, R2, p2)
+        if fx2 is not None:
+            m2 = fx2["meta"]
+            also["oracle_spread"] = {k: {q: m2[k][q] for q in ("sigma_norm", "sigma_max", "U", "V")}
+                                     for k in ("twin", "ordering_spread") if k in m2}
+        line["also"] = {args.also: also}
     if args.batched > 0:
         line["batched"] = batched_line(H, W, ctx, args.batched)
     if not args.no_cpu_baseline:
