@@ -280,12 +280,13 @@ hsvd_status hsvd_autotune(hsvd_ctx *ctx, int n, int *best_algo, int *best_wg);
  * The results of a batched solve do not depend on the width (bit-identical).
  * Then, with the chosen width, it times the two sweep schedules (one persistent
  * launch, launches grouped by order; batch_mode 0 and 1) in FP64 and in mixed
- * precision on the whole batch's orders (seeded synthetic entries as above:
- * the grouped launches gain with the number of problems per group, so a sample
- * would not tell) and keeps the faster per precision for hsvd_solve_batched
- * calls with batch_mode = 2 (hsvd_batched_schedule reports the choice).  Its
- * inputs and outputs take three times the batch's packed size in the context's
- * auxiliary device buffer, kept until hsvd_destroy.  With HSVD_AUTOTUNE_CACHE
+ * precision on the orders of all the given problems with n <= 256, up to
+ * 16384 of them (every k-th beyond; seeded synthetic entries as above: the
+ * grouped launches gain with the number of problems per group, so a small
+ * sample would not tell) and keeps the faster per precision for
+ * hsvd_solve_batched calls with batch_mode = 2 (hsvd_batched_schedule reports
+ * the choice).  Its inputs and outputs take three times their packed size in
+ * the context's auxiliary device buffer, kept until hsvd_destroy.  With HSVD_AUTOTUNE_CACHE
  * set the choices are written to that file too.
  *   n, p          device or host arrays of `batch` entries (as hsvd_solve_batched).
  *   best_threads  host, may be NULL: the chosen width.

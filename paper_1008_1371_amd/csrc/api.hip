@@ -1495,17 +1495,32 @@ extern "C" hsvd_status hsvd_autotune_batched(hsvd_ctx *ctx, int batch, const int
     }
     ctx->persist_threads[bucket] = best;
     // The sweep schedule per precision, with the chosen width: one persistent
-    // launch against launches grouped by order, timed on the whole batch (the
-    // grouped launches gain with the number of problems per group, so a
-    // sample would not tell).
-    std::vector<long long> aoff(batch), avoff(batch);
+    // launch against launches grouped by order, timed on the problems whose
+    // schedule it decides (n <= kPersistMaxOrder), all of them up to 16384
+    // (every k-th beyond): the grouped launches gain with the number of
+    // problems per group, so a small sample would not tell.
+    std::vector<int> an, ap;
+    {
+        int small = 0;
+        for (int k = 0; k < batch; ++k) small += n[k] <= kPersistMaxOrder ? 1 : 0;
+        const int stride2 = (small + 16383) / 16384;
+        int seen = 0;
+        for (int k = 0; k < batch; ++k) {
+            if (n[k] > kPersistMaxOrder) continue;
+            if (seen++ % stride2 == 0) {
+                an.push_back(n[k]);
+                ap.push_back(p[k]);
+            }
+        }
+    }
+    const int A = (int)an.size();
+    std::vector<long long> aoff(A), avoff(A);
     long long atot = 0, atotv = 0;
-    for (int k = 0; k < batch; ++k) {
-        if (n[k] < 1 || n[k] > 1024 || p[k] < 0 || p[k] > n[k]) return HSVD_E_INVAL;
+    for (int k = 0; k < A; ++k) {
         aoff[k] = atot;
         avoff[k] = atotv;
-        atot += (long long)n[k] * n[k];
-        atotv += n[k];
+        atot += (long long)an[k] * an[k];
+        atotv += an[k];
     }
     size_t oa = 0;
     const size_t a_G = take_bytes(oa, sizeof(double) * atot), a_U = take_bytes(oa, sizeof(double) * atot);
@@ -1514,8 +1529,8 @@ extern "C" hsvd_status hsvd_autotune_batched(hsvd_ctx *ctx, int batch, const int
     if (sa2 != HSVD_OK) return sa2;
     char *abase = static_cast<char *>(ctx->aux);
     double *AG = reinterpret_cast<double *>(abase + a_G);
-    for (int k = 0; k < batch; ++k)
-        HSVD_TRY(launch_synth(st, AG + aoff[k], n[k], 0x5C4EDull + (unsigned long long)k));
+    for (int k = 0; k < A; ++k)
+        HSVD_TRY(launch_synth(st, AG + aoff[k], an[k], 0x5C4EDull + (unsigned long long)k));
     for (int pr = 0; pr < 2; ++pr) {
         float sched_ms[2] = {0.f, 0.f};
         for (int mode = 0; mode < 2; ++mode) {
@@ -1525,7 +1540,7 @@ extern "C" hsvd_status hsvd_autotune_batched(hsvd_ctx *ctx, int batch, const int
             for (int rep = 0; rep < 2; ++rep) {  // the first run also warms up
                 HSVD_TRY(hipEventRecord(ev[0], st));
                 const hsvd_status s = hsvd_solve_batched(
-                    ctx, batch, n.data(), p.data(), aoff.data(), avoff.data(), AG, &q,
+                    ctx, A, an.data(), ap.data(), aoff.data(), avoff.data(), AG, &q,
                     reinterpret_cast<double *>(abase + a_s), reinterpret_cast<double *>(abase + a_U),
                     reinterpret_cast<double *>(abase + a_V), nullptr, nullptr);
                 if (s != HSVD_OK && s != HSVD_E_NOCONV) return s;
