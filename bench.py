@@ -38,14 +38,14 @@ MEASURED_TRAFFIC = {
     "mode": "mixed",
     "sources": ["paper_1008_1371_amd/csrc/block_kernels.hip", "paper_1008_1371_amd/csrc/block_device.h",
                 "paper_1008_1371_amd/csrc/api.hip", "paper_1008_1371_amd/csrc/internal.h"],
-    "sha256": "fb28f988831edf530ed1c4735b5c0d20b917fc5fd2a6fb4a1dcfee3ac35a98b7",
+    "sha256": "96cd9cc2c68702f0f293b817dcc5a7dc1795e8eda59fd44843a116c0c0e1375a",
     "bytes_per_launch": {
-        "block_gram_kernel<float>": (32858.3 * 2.0 + 5120.0 * 1.0) * 1024,
-        "block_inner_kernel<float>": (22293.3 * 2.0 + 37590.1 * 1.0) * 1024,
-        "block_update_kernel<float>": (20432.7 * 2.0 + 36758.4 * 1.0) * 1024,
+        "block_gram_kernel<float>": (32857.5 * 2.0 + 5120.0 * 1.0) * 1024,
+        "block_inner_kernel<float>": (22295.6 * 2.0 + 37597.7 * 1.0) * 1024,
+        "block_update_kernel<float>": (20393.2 * 2.0 + 36688.0 * 1.0) * 1024,
         "block_gram_kernel<double>": (65593.5 * 2.0 + 10240.0 * 1.0) * 1024,
-        "block_inner_kernel<double>": (27517.2 * 2.0 + 37493.5 * 1.0) * 1024,
-        "block_update_kernel<double>": (18363.2 * 2.0 + 35512.7 * 1.0) * 1024,
+        "block_inner_kernel<double>": (27532.4 * 2.0 + 37493.5 * 1.0) * 1024,
+        "block_update_kernel<double>": (18362.6 * 2.0 + 35512.7 * 1.0) * 1024,
     },
 }
 
