@@ -74,7 +74,7 @@ def measured_traffic(kernel, workload, mode):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="colscaled4096")
     ap.add_argument("--mode", default="both", choices=["both", "fp64", "mixed", "pairwise"],
@@ -364,7 +364,12 @@ def batched_line(H, W, ctx, count):
         R = H.hsvd_solve_batched(ctx, ns, ps, Gd, offs, voffs, prm)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        out[name] = {"seconds": dt, "solves_per_s": count / dt,
+        # algorithmic flops of the survey's count for a batch: 9 n^3 per sweep
+        # and problem (FP32 and FP64 sweeps alike), against the FP64 peak
+        sw = np.array([i["sweeps"] + i["sweeps_fp32"] for i in R["infos"]], dtype=np.float64)
+        gflop = float((sw * 9.0 * ns.astype(np.float64) ** 3).sum()) / 1e9
+        out[name] = {"seconds": dt, "solves_per_s": count / dt, "gflop_algorithmic": gflop,
+                     "tflops": gflop / dt / 1e3, "frac_fp64_peak": gflop / dt / 1e3 / FP64_PEAK_TFLOPS,
                      "max_sweeps_fp32": max(i["sweeps_fp32"] for i in R["infos"]),
                      "max_sweeps": int(R["sweeps"].max()), "all_converged": bool((R["statuses"] == 0).all()),
                      "fp64_restarts": sum(i["fp64_restart"] for i in R["infos"])}
