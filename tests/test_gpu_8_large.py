@@ -90,3 +90,33 @@ def test_graded8192_both_precisions(hsvd_ctx):
     # this kind of matrix and by 1.2e-9 in U; gates at about 10x those
     assert es <= 1e-11, es
     assert eu <= 1e-7 and ev <= 1e-7, (eu, ev)
+
+
+@pytest.mark.timeout(900)
+def test_max_order(hsvd_ctx):
+    """The largest order the library takes (bordered order r = 16384): a
+    column-scaled Gaussian (condition ~1e4) of order n = 16384, p = n/2, on
+    the mixed path, and the same matrix cut to n = 16383 (one border column)
+    on the FP64 block path, both against the invariants; one order more is
+    rejected before any launch."""
+    import torch
+
+    from paper_1008_1371_amd import hsvd as H
+    n = 16384
+    G = W.colscaled(n, 4.0, seed=16384)
+    for prec, m in ((1, n), (0, n - 1)):
+        Gt = torch.from_numpy(G[:m, :m]).cuda()
+        p = m // 2
+        say("max order: n", m, "p", p, "precision", prec)
+        R = H.hsvd_solve(hsvd_ctx, Gt, p, H.hsvd_default_params(algo=2, precision=prec), check=False)
+        i = R["info"]
+        say("   status", R["status"], "sweeps", i["sweeps_fp32"], i["sweeps"], "ms", i["ms_total"])
+        assert R["status"] == 0
+        check_invariants_gpu(Gt, p, R, tol=1e-15 * m, sweeps=i["sweeps"] + i["sweeps_fp32"])
+        del Gt, R
+        torch.cuda.empty_cache()
+    big = torch.zeros((n + 1, n + 1), dtype=torch.float64, device="cuda")
+    big.diagonal().fill_(1.0)
+    for algo in (1, 2):
+        R = H.hsvd_solve(hsvd_ctx, big, (n + 1) // 2, H.hsvd_default_params(algo=algo), check=False)
+        assert R["status"] == H.E_INVAL, (algo, R["status"])
