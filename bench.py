@@ -364,8 +364,8 @@ def batched_line(H, W, ctx, count):
         R = H.hsvd_solve_batched(ctx, ns, ps, Gd, offs, voffs, prm)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        # algorithmic flops of the survey's count for a batch: 9 n^3 per sweep
-        # and problem (FP32 and FP64 sweeps alike), against the FP64 peak
+        # algorithmic flops of a batch, counted as 9 n^3 per sweep and problem
+        # (FP32 and FP64 sweeps alike), against the FP64 peak
         sw = np.array([i["sweeps"] + i["sweeps_fp32"] for i in R["infos"]], dtype=np.float64)
         gflop = float((sw * 9.0 * ns.astype(np.float64) ** 3).sum()) / 1e9
         out[name] = {"seconds": dt, "solves_per_s": count / dt, "gflop_algorithmic": gflop,
@@ -380,7 +380,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "sharding is a design note, not a built path", file=sys.stderr)
+              "sharding is not built", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -52,9 +52,10 @@ typedef enum { HSVD_ORD_MODMOD = 0, HSVD_ORD_ROUNDROBIN = 1 } hsvd_ordering;
 
 typedef struct {
     int precision;   /* hsvd_precision: HSVD_FP64, or HSVD_MIXED = FP32 block sweeps on
-                        FP32 MFMA until they stop paying (switch rule of the design
-                        notes), FP64 J-re-orthogonalisation of V, then FP64 block
-                        sweeps.  If an FP32 sweep flags a pair as rank deficient, or
+                        FP32 MFMA until they stop paying (the largest rotation
+                        tangent or the rotating fraction stops falling, or falls
+                        below FP32 reach), FP64 J-re-orthogonalisation of V, then
+                        FP64 block sweeps.  If an FP32 sweep flags a pair as rank deficient, or
                         the re-orthogonalisation ends above reorth_accept, the solve
                         starts again from G in FP64 (hsvd_info.fp64_restart)           */
     int algo;        /* hsvd_algo                                                        */
@@ -146,7 +147,12 @@ typedef struct {
                                                 count the other steps of that sweep at
                                                 the mean of its timed ones              */
     long long kernel_launches[HSVD_NKERNELS];
-    double kernel_bytes[HSVD_NKERNELS];      /* algorithmic bytes (see the design notes) */
+    double kernel_bytes[HSVD_NKERNELS];      /* algorithmic bytes: the columns of G
+                                                and V a kernel class must read and
+                                                write (Gram: 2b columns per block
+                                                pair; update: the touched columns,
+                                                read and written; pairwise: two
+                                                columns per visit)                  */
     double kernel_flops[HSVD_NKERNELS];      /* algorithmic flops                        */
     long long kernel_timed[HSVD_NKERNELS];   /* launches that were timed by events      */
 } hsvd_info;

@@ -18,8 +18,8 @@
  *   - bordering of odd orders                                        (Sec. 4, eq. 4.1)
  *   - block-column ordering (inner pass over a pivot block)          (Sec. 5, block-oriented algorithm)
  *
- * Readings of ambiguous or garbled passages are the ones listed in the
- * repository design notes; each is restated where it is used in the .c file.
+ * Where the paper is ambiguous or garbled, the reading taken is restated
+ * where it is used in the .c file.
  */
 #ifndef HSVD_ORACLE_H
 #define HSVD_ORACLE_H
