@@ -77,8 +77,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="colscaled4096")
-    ap.add_argument("--mode", default="both", choices=["both", "fp64", "mixed", "pairwise"],
-                    help="both: mixed is the headline, FP64 block timed beside it")
+    ap.add_argument("--mode", default="both", choices=["both", "fp64", "mixed", "pairwise", "batched"],
+                    help="both: mixed is the headline, FP64 block timed beside it; batched: only the batched "
+                         "solver's persistent launch (FP64 and mixed, untuned width; profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the bounded oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -336,12 +337,14 @@ def timed(H, ctx, G, p, prm, out, steps, warmup, check):
     return 1000.0 * wall / steps, infos, R
 
 
-def batched_line(H, W, ctx, count):
+def batched_line(H, W, ctx, count, persistent_only=False):
     """The batched solver on `count` Gaussian problems, n ~ U{8..256}, FP64
     and mixed precision, with the sweep schedule and the persistent kernel's
     width the autotuner picks (tuned first, outside the timed runs), and each
     schedule on its own for comparison: one persistent launch, and launches
-    grouped by bordered order."""
+    grouped by bordered order.  persistent_only: the persistent launch alone,
+    FP64 and mixed, at the untuned width (one warm-up and one timed call each).
+    """
     import numpy as np
     import torch
     ns, ps, Gs = W.batch(count)
@@ -349,14 +352,16 @@ def batched_line(H, W, ctx, count):
     voffs = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
     Gd = torch.from_numpy(flat).cuda()
     out = {"problems": count, "n_range": [int(ns.min()), int(ns.max())]}
-    # the persistent kernel's width for this size mix (outside the timed runs)
-    best, widths = H.hsvd_autotune_batched(ctx, ns, ps)
-    out["persistent_width"] = {"threads": best, "autotune_ms": widths}
-    out["schedule"] = {name: ("persistent", "grouped")[H.hsvd_batched_schedule(ctx, prec)]
-                       for name, prec in (("fp64", H.FP64), ("mixed", H.MIXED))}
-    for name, prec, mode in (("fp64", H.FP64, 2), ("mixed", H.MIXED, 2), ("fp64_persistent", H.FP64, 0),
-                             ("fp64_grouped", H.FP64, 1), ("mixed_persistent", H.MIXED, 0),
-                             ("mixed_grouped", H.MIXED, 1)):
+    configs = (("fp64_persistent", H.FP64, 0), ("mixed_persistent", H.MIXED, 0))
+    if not persistent_only:
+        # the persistent kernel's width for this size mix (outside the timed runs)
+        best, widths = H.hsvd_autotune_batched(ctx, ns, ps)
+        out["persistent_width"] = {"threads": best, "autotune_ms": widths}
+        out["schedule"] = {name: ("persistent", "grouped")[H.hsvd_batched_schedule(ctx, prec)]
+                           for name, prec in (("fp64", H.FP64), ("mixed", H.MIXED))}
+        configs = ((("fp64", H.FP64, 2), ("mixed", H.MIXED, 2)) + configs[:1] + (("fp64_grouped", H.FP64, 1),) +
+                   configs[1:] + (("mixed_grouped", H.MIXED, 1),))
+    for name, prec, mode in configs:
         prm = H.hsvd_default_params(precision=prec, batch_mode=mode)
         H.hsvd_solve_batched(ctx, ns, ps, Gd, offs, voffs, prm)  # warm-up
         torch.cuda.synchronize()
@@ -399,6 +404,9 @@ def main():
         return
 
     H.lib()  # fails loudly if the HIP library is missing
+    if args.mode == "batched":
+        print(json.dumps({"batched": batched_line(H, W, H.Context(0), args.batched or 10000, True)}), flush=True)
+        return
     G_np, p = W.workload(args.workload)
     n = G_np.shape[0]
     # the prescribed spectrum of an eigen workload (cached by the generator)
