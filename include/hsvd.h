@@ -242,8 +242,9 @@ hsvd_status hsvd_solve_noalloc(hsvd_ctx *ctx, const double *G, int lda, int n, i
  *                    skips, active_pairs; ms_total is the device time of the
  *                    whole batched call; the kernel_* arrays are zero.
  * Problems of the block-oriented method with n <= 256 run in one persistent
- * launch (prm->batch_mode = 0, the default; captured as a HIP graph when
- * prm->graph is set): each workgroup takes problems from a device work queue,
+ * launch (prm->batch_mode = 0; with the default 2, before tuning or when
+ * hsvd_autotune_batched chose it for the precision; captured as a HIP graph
+ * when prm->graph is set): each workgroup takes problems from a device work queue,
  * largest n first, and solves each one completely -- Gram, inner rotations
  * and update of every block pair, sort and the stop rule of eq. (4.2) per
  * sweep; with mixed precision first the FP32 sweeps, the switch rule and the
