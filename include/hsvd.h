@@ -249,8 +249,9 @@ hsvd_status hsvd_solve_noalloc(hsvd_ctx *ctx, const double *G, int lda, int n, i
  * and update of every block pair, sort and the stop rule of eq. (4.2) per
  * sweep; with mixed precision first the FP32 sweeps, the switch rule and the
  * J-re-orthogonalisation of V -- then output extraction, with no host round
- * trip.  The other problems (n > 256, the full-block method, or
- * batch_mode = 1) are grouped by their bordered order (a multiple of 2b); each
+ * trip.  The other problems (n > 256, the full-block method, batch_mode = 1,
+ * or 2 when tuning chose the grouped launches) are grouped by their bordered
+ * order (a multiple of 2b); each
  * group runs as one sequence of launches that covers all of its problems,
  * with the stop rule decided per problem on the device.  In FP64 both forms
  * give bit-identical results (in mixed precision see batch_mode).  Returns
