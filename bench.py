@@ -38,14 +38,14 @@ MEASURED_TRAFFIC = {
     "mode": "mixed",
     "sources": ["paper_1008_1371_amd/csrc/block_kernels.hip", "paper_1008_1371_amd/csrc/block_device.h",
                 "paper_1008_1371_amd/csrc/api.hip", "paper_1008_1371_amd/csrc/internal.h"],
-    "sha256": "96cd9cc2c68702f0f293b817dcc5a7dc1795e8eda59fd44843a116c0c0e1375a",
+    "sha256": "54ce685e23de08f1ffb633d6140eefc89c1d8bfb733bdb02c46b1f8449305e53",
     "bytes_per_launch": {
-        "block_gram_kernel<float>": (32857.5 * 2.0 + 5120.0 * 1.0) * 1024,
-        "block_inner_kernel<float>": (22295.6 * 2.0 + 37597.7 * 1.0) * 1024,
-        "block_update_kernel<float>": (20393.2 * 2.0 + 36688.0 * 1.0) * 1024,
+        "block_gram_kernel<float>": (32853.2 * 2.0 + 5120.0 * 1.0) * 1024,
+        "block_inner_kernel<float>": (22295.7 * 2.0 + 37575.6 * 1.0) * 1024,
+        "block_update_kernel<float>": (20340.1 * 2.0 + 35950.4 * 1.0) * 1024,
         "block_gram_kernel<double>": (65593.5 * 2.0 + 10240.0 * 1.0) * 1024,
-        "block_inner_kernel<double>": (27532.4 * 2.0 + 37493.5 * 1.0) * 1024,
-        "block_update_kernel<double>": (18362.6 * 2.0 + 35512.7 * 1.0) * 1024,
+        "block_inner_kernel<double>": (27488.0 * 2.0 + 37493.5 * 1.0) * 1024,
+        "block_update_kernel<double>": (20033.4 * 2.0 + 35511.7 * 1.0) * 1024,
     },
 }
 
